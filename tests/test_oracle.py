@@ -1,0 +1,338 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's own formula: MTTKRP is checked against a
+dense unfolding times a Khatri-Rao product, closed forms and invariants;
+Algorithm 1 against the paper's worked example, Graham's bound and brute
+force; CP-ALS against exact recovery, monotonicity and a dense residual.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_08470_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _khatri_rao(mats):
+    """Column-wise Kronecker product; the last matrix's row index varies fastest."""
+    out = mats[0]
+    for m in mats[1:]:
+        out = np.einsum("ir,jr->ijr", out, m).reshape(-1, m.shape[1])
+    return out
+
+
+# ---------------------------------------------------------------- MTTKRP
+
+TINY = [((7, 6, 5), 60), ((5, 4, 3, 3), 70), ((4, 3, 3, 2, 2), 50), ((6, 5), 20)]
+
+
+@pytest.mark.parametrize("dims,nnz", TINY)
+def test_mttkrp_equals_dense_unfolding_times_khatri_rao(dims, nnz):
+    # Sec. 2.1.4: M_d = X_(d) (Khatri-Rao of the other factors); with repeats
+    idx, val = synth.random_coo(dims, nnz, seed=11)
+    idx[:, nnz // 2:nnz // 2 + 5] = idx[:, :5]  # force repeated coordinates
+    Y = synth.random_factors(dims, 4, seed=12)
+    X = oracle.full_tensor(dims, idx, val)
+    for d in range(len(dims)):
+        others = [w for w in range(len(dims)) if w != d]
+        Xd = np.moveaxis(X, d, 0).reshape(dims[d], -1)
+        K = _khatri_rao([Y[w].astype(np.float64) for w in others])
+        assert _rel(oracle.mttkrp(dims, idx, val, Y, d), Xd @ K) < 1e-13
+
+
+def test_mttkrp_matches_cyclic_form_of_eq1():
+    # Eq. (1): A~ = X_(0)(B kr C), B~ = X_(1)(C kr A), C~ = X_(2)(A kr B)
+    dims = (6, 5, 4)
+    idx, val = synth.random_coo(dims, 40, seed=3)
+    A, B, C = [y.astype(np.float64) for y in synth.random_factors(dims, 3, seed=4)]
+    X = oracle.full_tensor(dims, idx, val)
+    X0 = X.reshape(6, 20)                             # columns (j, k), k fastest
+    X1 = np.transpose(X, (1, 2, 0)).reshape(5, 24)    # columns (k, i), i fastest
+    X2 = np.transpose(X, (2, 0, 1)).reshape(4, 30)    # columns (i, j), j fastest
+    Y = [A, B, C]
+    assert _rel(oracle.mttkrp(dims, idx, val, Y, 0), X0 @ _khatri_rao([B, C])) < 1e-13
+    assert _rel(oracle.mttkrp(dims, idx, val, Y, 1), X1 @ _khatri_rao([C, A])) < 1e-13
+    assert _rel(oracle.mttkrp(dims, idx, val, Y, 2), X2 @ _khatri_rao([A, B])) < 1e-13
+
+
+@pytest.mark.parametrize("N", [3, 4, 5])
+def test_mttkrp_rank_one_closed_form(N):
+    # X = lam * a1 o a2 o ... o aN with sparse vectors:
+    # M_d(i, r) = lam * a_d(i) * prod_{w != d} <a_w, Y_w[:, r]>
+    rng = np.random.default_rng(5 + N)
+    dims = [9, 7, 6, 5, 4][:N]
+    vecs, supp = [], []
+    for I in dims:
+        s = np.sort(rng.choice(I, size=3, replace=False))
+        v = np.zeros(I)
+        v[s] = rng.uniform(0.5, 1.5, size=3)
+        vecs.append(v)
+        supp.append(s)
+    lam = 1.75
+    coords = np.array(list(itertools.product(*supp))).T.astype(np.int32)
+    val = lam * np.prod([vecs[w][coords[w]] for w in range(N)], axis=0)
+    Y = [rng.standard_normal((I, 3)) for I in dims]
+    for d in range(N):
+        expect = lam * np.outer(vecs[d], np.prod(
+            [vecs[w] @ Y[w] for w in range(N) if w != d], axis=0))
+        got = oracle.mttkrp(dims, coords, val, Y, d)
+        assert _rel(got, expect) < 1e-13
+
+
+def test_mttkrp_cross_mode_invariant_and_linearity():
+    # sum_{i,r} M_d(i,r) Y_d(i,r) = <X, [[Y]]> for every d; linear in val;
+    # invariant under any reordering of the COO list; column r of the result
+    # depends only on column r of the factors.
+    dims = (8, 6, 7, 5)
+    idx, val = synth.random_coo(dims, 200, seed=21)
+    val = val.astype(np.float64)
+    Y = [y.astype(np.float64) for y in synth.random_factors(dims, 5, seed=22)]
+    inner = [np.sum(oracle.mttkrp(dims, idx, val, Y, d) * Y[d]) for d in range(4)]
+    assert max(inner) - min(inner) < 1e-11 * max(1.0, abs(inner[0]))
+    perm = np.random.default_rng(0).permutation(200)
+    for d in range(4):
+        M = oracle.mttkrp(dims, idx, val, Y, d)
+        assert _rel(oracle.mttkrp(dims, idx, 2.5 * val, Y, d), 2.5 * M) < 1e-14
+        assert _rel(oracle.mttkrp(dims, idx[:, perm], val[perm], Y, d), M) < 1e-13
+        Y2 = [y.copy() for y in Y]
+        for w in range(4):
+            Y2[w][:, 3] += 1.0
+        M2 = oracle.mttkrp(dims, idx, val, Y2, d)
+        assert np.array_equal(np.delete(M2, 3, axis=1), np.delete(M, 3, axis=1))
+        assert not np.allclose(M2[:, 3], M[:, 3])
+
+
+def test_mttkrp_empty_rows_are_zero_and_bad_index_rejected():
+    dims = (10, 4, 3)
+    idx = np.array([[2, 2, 7], [0, 1, 3], [2, 0, 1]], dtype=np.int32)
+    val = np.array([1.0, 2.0, 3.0], dtype=np.float32)
+    Y = synth.random_factors(dims, 2, seed=1)
+    M = oracle.mttkrp(dims, idx, val, Y, 0)
+    assert np.all(M[[0, 1, 3, 4, 5, 6, 8, 9]] == 0)
+    bad = idx.copy()
+    bad[1, 0] = 4
+    with pytest.raises(ValueError):
+        oracle.mttkrp(dims, bad, val, Y, 0)
+    assert np.all(oracle.mttkrp(dims, idx[:, :0], val[:0], Y, 2) == 0)
+
+
+# ---------------------------------------------------------------- Alg. 1
+
+def test_partition_worked_example():
+    with open(os.path.join(GOLDEN, "partition_example.json")) as f:
+        g = json.load(f)
+    idx = np.array(g["hyperedges"], dtype=np.int32).T
+    p = oracle.plan(g["dims"], idx, g["kappa"], split_cap=0)
+    exp = g["expect_mode0"]
+    assert p["deg"][0].tolist() == exp["degree"]
+    blocks = {int(r): int(z) for r, z in zip(p["item_rows"][0], p["item_part"][0])}
+    assert [blocks[v] for v in range(3)] == exp["block_of_vertex"]
+    assert p["loads"][0].tolist() == exp["block_loads"]
+
+
+def test_lpt_graham_tight_instance():
+    # Graham (1969): sizes {3,3,2,2,2} on 2 machines; LPT makespan 7, OPT 6,
+    # ratio 4/3 - 1/(3*2).  Pins the decreasing order and least-filled rule.
+    part, loads = oracle.lpt(np.array([3, 3, 2, 2, 2]), 2)
+    assert part.tolist() == [0, 1, 0, 1, 0]
+    assert loads.tolist() == [7, 5]
+
+
+def _opt_makespan(sizes, k):
+    best = None
+    for assign in itertools.product(range(k), repeat=len(sizes)):
+        loads = [0] * k
+        for s, a in zip(sizes, assign):
+            loads[a] += s
+        m = max(loads)
+        best = m if best is None else min(best, m)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_lpt_within_four_thirds_of_brute_force_optimum(seed):
+    # Sec. 3.4.1: the partitioning is at most 4/3 of the optimal makespan.
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(2, 4))
+    n = int(rng.integers(k + 1, 9))
+    deg = rng.integers(1, 20, size=n)
+    rows, pieces, sizes = oracle.lpt_items(deg, cap=0)
+    _, loads = oracle.lpt(sizes, k)
+    opt = _opt_makespan(deg.tolist(), k)
+    assert loads.max() <= (4.0 / 3.0 - 1.0 / (3 * k)) * opt + 1e-9
+    assert loads.sum() == deg.sum()
+
+
+def test_lpt_ties_go_to_lowest_block_and_zero_degree_rows_are_items():
+    rows, pieces, sizes = oracle.lpt_items(np.array([0, 2, 2, 1, 0]), cap=0)
+    assert rows.tolist() == [1, 2, 3, 0, 4]
+    part, loads = oracle.lpt(sizes, 3)
+    assert part.tolist() == [0, 1, 2, 2, 2]
+
+
+def test_split_pieces():
+    rows, pieces, sizes = oracle.lpt_items(np.array([10, 3, 7]), cap=4)
+    got = sorted(zip(rows.tolist(), pieces.tolist(), sizes.tolist()))
+    assert got == [(0, 0, 4), (0, 1, 3), (0, 2, 3), (1, 0, 3), (2, 0, 4), (2, 1, 3)]
+    # pieces take the row's nonzeros in input order
+    row_of_e = np.array([0] * 10 + [2] * 7)
+    pc = oracle.piece_of_nonzero(row_of_e, np.array([10, 0, 7]), cap=4)
+    assert pc.tolist() == [0] * 4 + [1] * 3 + [2] * 3 + [0] * 4 + [1] * 3
+
+
+def _check_plan_invariants(dims, idx, p, kappa):
+    N, nnz = idx.shape
+    for d in range(N):
+        b = p["b"][d]
+        # Observation 1: remap ids are a permutation of [0, nnz)
+        assert np.array_equal(np.sort(b), np.arange(nnz))
+        assert np.array_equal(b[p["order"][d]], np.arange(nnz))
+        # partitions are contiguous and match ptr / loads
+        z = p["part"][d]
+        assert p["ptr"][d][-1] == nnz and p["loads"][d].sum() == nnz
+        zs = z[p["order"][d]]
+        assert np.all(np.diff(zs) >= 0)
+        for k in range(kappa):
+            assert np.all(zs[p["ptr"][d][k]:p["ptr"][d][k + 1]] == k)
+        # Observation 2 (unsplit rows): every nonzero of a row is in one block
+        deg = p["deg"][d]
+        ipieces = np.zeros(dims[d], dtype=np.int64)
+        np.add.at(ipieces, p["item_rows"][d], 1)
+        rows = idx[d]
+        for r in np.unique(rows):
+            if ipieces[r] == 1:
+                assert np.unique(z[rows == r]).size == 1
+        assert np.array_equal(np.bincount(rows, minlength=dims[d]), deg)
+    # Sec. 3.1: within each block the mode-0 stream follows the mode-0 index
+    s0 = idx[0][p["order"][0]]
+    z0 = p["part"][0][p["order"][0]]
+    same = z0[1:] == z0[:-1]
+    assert np.all(s0[1:][same] >= s0[:-1][same])
+
+
+@pytest.mark.parametrize("dims,nnz,kappa,cap", [((7, 6, 5), 80, 3, None), ((5, 4, 3, 3), 90, 4, 0),
+                                                ((4, 3, 3, 2, 2), 60, 5, None), ((30, 20), 200, 6, 5)])
+def test_plan_invariants_and_stream_order_by_brute_force(dims, nnz, kappa, cap):
+    idx, _ = synth.random_coo(dims, nnz, seed=9, dist="zipf", zipf_s=1.3)
+    p = oracle.plan(dims, idx, kappa, split_cap=cap)
+    _check_plan_invariants(dims, idx, p, kappa)
+    N = len(dims)
+    z = p["part"]
+    for d in range(N):
+        def key(e):
+            k = []
+            for j in range(N):
+                w = (d - j) % N
+                k += [int(z[w][e]), int(idx[w][e])]
+            return tuple(k) + (e,)
+        assert p["order"][d].tolist() == sorted(range(nnz), key=key)
+
+
+def test_split_balances_a_hot_row():
+    # one row with 60 % of the nonzeros: pure Alg. 1 cannot balance it, the
+    # split extension brings the largest block to about nnz / kappa.
+    nnz, kappa = 1000, 8
+    rng = np.random.default_rng(2)
+    rows = np.where(rng.uniform(size=nnz) < 0.6, 0, rng.integers(1, 50, size=nnz))
+    idx = np.stack([rows, rng.integers(0, 9, size=nnz), rng.integers(0, 7, size=nnz)]).astype(np.int32)
+    dims = (50, 9, 7)
+    whole = oracle.plan(dims, idx, kappa, split_cap=0)
+    split = oracle.plan(dims, idx, kappa)
+    assert whole["loads"][0].max() >= 0.55 * nnz
+    assert split["loads"][0].max() <= 2 * oracle.default_cap(nnz, kappa)
+    _check_plan_invariants(dims, idx, split, kappa)
+
+
+# ---------------------------------------------------------------- CP-ALS
+
+def _planted(dims, R, supp, seed):
+    rng = np.random.default_rng(seed)
+    F = [np.zeros((I, R)) for I in dims]
+    for w, I in enumerate(dims):
+        rows = rng.permutation(I)[: R * supp[w]].reshape(R, supp[w])
+        for r in range(R):
+            F[w][rows[r], r] = rng.uniform(0.5, 1.5, size=supp[w])
+    coords, vals = [], []
+    for r in range(R):
+        sets = [np.nonzero(F[w][:, r])[0] for w in range(len(dims))]
+        for c in itertools.product(*sets):
+            coords.append(c)
+            vals.append(np.prod([F[w][c[w], r] for w in range(len(dims))]))
+    return np.array(coords, dtype=np.int32).T, np.array(vals)
+
+
+def _dense_model(Y, lam):
+    N = len(Y)
+    letters = "abcdefgh"[:N]
+    expr = ",".join(f"{l}r" for l in letters) + ",r->" + letters
+    return np.einsum(expr, *Y, lam)
+
+
+@pytest.mark.parametrize("dims,R,supp", [((60, 50, 40), 3, (8, 6, 5)),
+                                         ((20, 18, 16, 14), 2, (4, 3, 3, 3)),
+                                         ((12, 11, 10, 9, 8), 2, (3, 3, 2, 2, 2))])
+def test_cp_als_recovers_planted_low_rank(dims, R, supp):
+    # ALS from a random start can stall in a local minimum (two components on
+    # one block); the best of three seeded starts must reach the exact model.
+    idx, val = _planted(dims, R, supp, seed=7)
+    runs = [oracle.cp_als(dims, idx, val, synth.random_factors(dims, R, seed=s), iters=80)
+            for s in (8, 9, 10)]
+    Y, lam, fits = max(runs, key=lambda t: t[2][-1])
+    assert fits[-1] >= 1 - 1e-6
+    X = oracle.full_tensor(dims, idx, val)
+    res = np.linalg.norm(X - _dense_model(Y, lam)) / np.linalg.norm(X)
+    assert abs((1 - res) - fits[-1]) < 1e-7
+
+
+def test_cp_als_rank_one_converges_in_one_sweep():
+    dims = (9, 8, 7)
+    idx, val = _planted(dims, 1, (4, 3, 3), seed=3)
+    Y0 = synth.random_factors(dims, 1, seed=4)
+    _, _, fits = oracle.cp_als(dims, idx, val, Y0, iters=1)
+    assert fits[0] > 1 - 1e-12
+
+
+def test_cp_als_residual_is_monotone_and_fit_matches_dense_residual():
+    dims = (9, 8, 7, 6)
+    idx, val = synth.random_coo(dims, 150, seed=31)
+    idx[:, 100:110] = idx[:, :10]  # repeated coordinates
+    N, R = 4, 3
+    Y = [y.astype(np.float64) for y in synth.random_factors(dims, R, seed=32)]
+    X = oracle.full_tensor(dims, idx, val)
+    grams = [y.T @ y for y in Y]
+    prev = np.inf
+    for it in range(4):
+        for d in range(N):
+            M = oracle.mttkrp(dims, idx, val, Y, d)
+            Y[d], lam = oracle.als_update(M, grams, d)
+            grams[d] = Y[d].T @ Y[d]
+            res = np.linalg.norm(X - _dense_model(Y, lam))
+            assert res <= prev * (1 + 1e-12)
+            prev = res
+        f = oracle.fit_from(oracle.norm_sq(dims, idx, val), M, Y[N - 1], lam, grams)
+        assert abs(f - (1 - res / np.linalg.norm(X))) < 1e-10
+
+
+def test_norm_sq_sums_repeated_coordinates_first():
+    dims = (4, 3, 2)
+    idx = np.array([[1, 1, 2], [2, 2, 0], [1, 1, 1]], dtype=np.int32)
+    val = np.array([1.0, 2.0, -4.0])
+    assert oracle.norm_sq(dims, idx, val) == 9.0 + 16.0
+
+
+def test_not_spd_raises_after_one_ridge_retry():
+    G = [np.zeros((2, 2)), np.eye(2), np.eye(2)]
+    M = np.ones((3, 2))
+    with pytest.raises(oracle.NotSPD):
+        oracle.als_update(M, [np.zeros((2, 2)), np.zeros((2, 2)), np.eye(2)], 2)
+    Y, lam = oracle.als_update(M, G, 0)
+    assert np.allclose(np.linalg.norm(Y, axis=0), 1.0)
