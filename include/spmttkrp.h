@@ -1,0 +1,190 @@
+/*
+ * spmttkrp.h -- C ABI of the MI355X (gfx950) sparse MTTKRP library.
+ *
+ * Sparse MTTKRP over every mode of an N-mode COO tensor inside CP-ALS, with
+ * the tensor partitioned per mode by output row (Algorithm 1, Sec. 3.4) and
+ * remapped into the next mode's order while each mode is computed (dynamic
+ * tensor remapping, Sec. 3.1 and Algorithm 3), so that every output row is
+ * accumulated by exactly one workgroup, without global atomics and without
+ * intermediate results in HBM (Observations 1 and 2, Sec. 4.3).
+ *
+ * Conventions for every call:
+ *  - Every call returns spt_status; nothing throws across the ABI.  A
+ *    failing call leaves a thread-local message in spt_last_error().
+ *  - "device" pointers are HIP device allocations of the current device;
+ *    "host" pointers are ordinary host memory.  Nothing a caller passes is
+ *    kept after the call returns, except the handle the library allocated.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued asynchronously on it unless stated otherwise.
+ *  - Indices are 0-based int32, values FP32.  Dimensions and nnz must be
+ *    below 2^31; 2 <= nmodes <= 8.  Ranks 8, 16, 32, 64 and 128 are compiled.
+ *  - Factor matrices are row-major I_w x R; FP32 (SPT_F32) storage.
+ */
+#ifndef SPMTTKRP_H
+#define SPMTTKRP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spt_status {
+    SPT_OK = 0,
+    SPT_ERR_INVALID_ARG = 1,   /* NULL where a pointer is required, bad sizes   */
+    SPT_ERR_OUT_OF_RANGE = 2,  /* index outside its mode, size beyond int32    */
+    SPT_ERR_OOM = 3,           /* host or device allocation failed              */
+    SPT_ERR_HIP = 4,           /* a HIP runtime call failed                     */
+    SPT_ERR_STATE = 5,         /* tensor not in the order the call requires     */
+    SPT_ERR_NOT_SPD = 6,       /* ALS normal matrix not positive definite       */
+    SPT_ERR_UNSUPPORTED = 7    /* rank / mode count / layout not compiled       */
+} spt_status;
+
+typedef enum spt_dtype { SPT_F32 = 0 } spt_dtype;
+
+typedef struct spt_tensor_s *spt_tensor_t;  /* opaque, owned by the library */
+
+/* Options of spt_tensor_load_coo; NULL means all defaults. */
+typedef struct spt_opts {
+    int32_t kappa;      /* partitions per mode (kappa of Alg. 1); 0 = default:
+                           min(8 * #CUs, max(1, nnz / 1024))                  */
+    int32_t copies;     /* 0 = one tensor copy plus its remapping target
+                           (the paper's dynamic remapping); 1 = one
+                           mode-ordered copy per mode, no remapping needed  */
+    int64_t split_cap;  /* rows with more nonzeros are cut into pieces of at
+                           most this many (extension to Alg. 1, see
+                           spt_plan_coo); 0 = ceil(nnz / kappa); -1 = never  */
+    int32_t reserved[4];/* must be zero                                      */
+} spt_opts;
+
+/* Summary of a loaded tensor (spt_tensor_info). */
+typedef struct spt_info {
+    int32_t nmodes;
+    int32_t cur_mode;        /* mode whose order the stream is in            */
+    int32_t kappa;
+    int32_t record_bytes;    /* bytes of one packed nonzero record (16/32)   */
+    int64_t nnz;
+    int64_t dims[8];
+    int64_t max_load[8];     /* largest partition of each mode (nonzeros)    */
+    int64_t split_rows[8];   /* rows cut into pieces, per mode               */
+    double norm_sq;          /* ||X||_F^2 with repeated coordinates summed   */
+    double prep_seconds;     /* host preprocessing time of the load          */
+    int64_t device_bytes;    /* device memory held by the handle             */
+} spt_info;
+
+/* mttkrp flags */
+#define SPT_FUSE_REMAP_NEXT 1u  /* also scatter the stream into mode (d+1)'s
+                                   order (Alg. 3 fused with Alg. 2)           */
+#define SPT_AUTO_REMAP 2u       /* remap first if the stream is not in mode d */
+
+/*
+ * spt_tensor_load_coo -- preprocess a COO tensor and upload it (Sec. 3.4-3.5,
+ * Algorithm 5's input: the tensor ordered by mode 0).
+ *   nmodes   number of modes N, 2..8
+ *   dims     host int64[N], each in [1, 2^31)
+ *   nnz      number of nonzeros, in [0, 2^31)
+ *   indices  host int32, mode-major [N][nnz], 0-based
+ *   values   host float[nnz]
+ *   opts     host, may be NULL
+ *   stream   uploads are enqueued on it; the call returns after they finish
+ *   out      receives the handle; free it with spt_tensor_free
+ * Per mode: degrees, rows ordered by degree, least-filled assignment to
+ * kappa partitions, remap ids, then the packed mode-0 stream.  Inputs are
+ * copied.  Errors: INVALID_ARG, OUT_OF_RANGE (index outside its mode),
+ * UNSUPPORTED (index bits do not fit a 32-byte record), OOM, HIP.
+ */
+spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t *dims, int64_t nnz,
+                               const int32_t *indices, const float *values,
+                               const spt_opts *opts, void *stream, spt_tensor_t *out);
+
+/*
+ * spt_remap_for_mode -- reorder the stream into `mode`'s order (dynamic
+ * remapping, Sec. 3.1) by following each nonzero's remap ids; one scatter.
+ * No effect if the stream is already in that order.  Errors: INVALID_ARG.
+ */
+spt_status spt_remap_for_mode(spt_tensor_t t, int32_t mode, void *stream);
+
+/*
+ * spt_mttkrp -- spMTTKRP for one output mode (Eq. 1; Algorithms 2-4):
+ *   out(i, r) = sum_{nonzeros e with i_mode(e) = i} val(e) *
+ *               prod_{w != mode} factors[w](i_w(e), r)
+ *   factors  host array of nmodes device pointers, row-major I_w x rank;
+ *            factors[mode] is not read and may be NULL
+ *   rank     8, 16, 32, 64 or 128
+ *   out      device float, I_mode x rank row-major; OVERWRITTEN (rows with no
+ *            nonzero are set to zero)
+ *   flags    SPT_FUSE_REMAP_NEXT and/or SPT_AUTO_REMAP
+ * The stream must be in `mode`'s order (see spt_tensor_info) unless
+ * SPT_AUTO_REMAP is set; otherwise STATE.  With SPT_FUSE_REMAP_NEXT the
+ * stream is left in mode (mode+1) mod N's order.  With one copy per mode
+ * (opts.copies = 1) any mode may be computed at any time and the flags have
+ * no effect.  No global atomics: each output row is written once.
+ */
+spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void *const *factors,
+                      spt_dtype fdtype, int32_t rank, float *out, uint32_t flags,
+                      void *stream);
+
+/*
+ * spt_cp_als_iter -- one CP-ALS sweep over modes 0..N-1 (Sec. 2.1.4;
+ * Algorithm 5 extended with the least-squares update of each factor):
+ * per mode d, M = mttkrp(d) fused with the remap to d+1; V = Hadamard
+ * product of the other factors' Grams (FP64); Y_d = M V^-1 via Cholesky in
+ * FP64 (one ridge retry of 1e-12 tr(V)/R, else NOT_SPD); columns of Y_d
+ * scaled to unit 2-norm, lambda = the norms.
+ *   factors  host array of nmodes device float pointers, updated in place
+ *   lambda   device double[rank], receives the column norms of the last mode
+ *   fit      host double*, receives 1 - ||X - Xhat|| / ||X|| (synchronises
+ *            the stream); NULL to skip
+ * The stream must be in mode 0's order on entry and is on exit.
+ * Device workspace is allocated on first use per rank and kept by the
+ * handle.  Errors: STATE, UNSUPPORTED, NOT_SPD (reported by the call that
+ * synchronises: this one when fit != NULL, else the next), HIP, OOM.
+ */
+spt_status spt_cp_als_iter(spt_tensor_t t, void *const *factors, spt_dtype fdtype,
+                           int32_t rank, double *lambda, double *fit, void *stream);
+
+/* spt_tensor_info -- fills *info (host). */
+spt_status spt_tensor_info(spt_tensor_t t, spt_info *info);
+
+/*
+ * spt_tensor_get_remap -- remap ids of `mode` as the device holds them:
+ * b_host[e] (host int64[nnz]) = position of input nonzero e in mode's
+ * stream.  Synchronous.
+ */
+spt_status spt_tensor_get_remap(spt_tensor_t t, int32_t mode, int64_t *b_host);
+
+/*
+ * spt_tensor_get_records -- copies the current stream back and unpacks it:
+ * idx_host int32 [N][nnz] and val_host float[nnz] in stream order, plus the
+ * mode whose order it is in.  Synchronous.
+ */
+spt_status spt_tensor_get_records(spt_tensor_t t, int32_t *idx_host, float *val_host,
+                                  int32_t *cur_mode);
+
+/* spt_tensor_free -- releases the handle and its device memory (NULL ok). */
+spt_status spt_tensor_free(spt_tensor_t t);
+
+/*
+ * spt_plan_coo -- host-only preprocessing, no device needed (for inspection
+ * and tests).  Same validation and options as spt_tensor_load_coo.  Outputs
+ * (host, caller-allocated, any may be NULL):
+ *   part  int32 [N][nnz]   partition of each nonzero in each mode
+ *   remap int64 [N][nnz]   remap id b_d(e) = position in mode d's stream
+ *   ptr   int64 [N][kappa+1] partition offsets of each stream
+ *   kappa_out              the kappa used
+ */
+spt_status spt_plan_coo(int32_t nmodes, const int64_t *dims, int64_t nnz,
+                        const int32_t *indices, const spt_opts *opts, int32_t *part,
+                        int64_t *remap, int64_t *ptr, int32_t *kappa_out);
+
+/* Human-readable name of a status. */
+const char *spt_status_str(spt_status s);
+
+/* Detail of the last failure on this thread ("" if none). */
+const char *spt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPMTTKRP_H */

@@ -1,0 +1,541 @@
+// C ABI of the library (include/spmttkrp.h): handle lifecycle, uploads,
+// kernel launches and the CP-ALS sweep.
+#include "spmttkrp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using spt::Plan;
+using spt::PlanOptions;
+using spt::RecordLayout;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+spt_status fail(spt_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+spt_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? SPT_ERR_OOM : SPT_ERR_HIP;
+}
+
+#define HIPCHK(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+bool rank_compiled(int r) { return r == 8 || r == 16 || r == 32 || r == 64 || r == 128; }
+bool als_rank(int r) { return r == 8 || r == 16 || r == 32 || r == 64; }
+
+}  // namespace
+
+struct spt_tensor_s {
+    int N = 0;
+    int64_t nnz = 0;
+    int64_t dims[8] = {};
+    int32_t kappa = 0;
+    int copies = 0;
+    int cur_mode = 0;
+    RecordLayout lay;
+    // device: record streams.  copies == 0: rec[cur] holds the stream of
+    // cur_mode, rec[1-cur] is the remap target.  copies == 1: rec_mode[d].
+    uint32_t* rec[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint32_t* rec_mode[8] = {};
+    int32_t* nxt[8] = {};
+    int64_t* ptr[8] = {};
+    int32_t* psplit_ptr[8] = {};
+    int32_t* psplit_row[8] = {};
+    int32_t* psplit_slot[8] = {};
+    int32_t* split_row[8] = {};
+    int32_t* split_ptr[8] = {};
+    int32_t* empty_rows[8] = {};
+    int32_t nsplit[8] = {}, nslots[8] = {}, nempty[8] = {};
+    int64_t max_load[8] = {};
+    std::vector<int32_t> order0;  // input nonzero at each mode-0 position
+    double norm_sq = 0.0;
+    double prep_seconds = 0.0;
+    int64_t device_bytes = 0;
+    std::vector<void*> allocs;
+    // workspace
+    int ws_rank = 0;
+    float* M = nullptr;
+    float* carry = nullptr;
+    double* grams = nullptr;
+    double* gpart = nullptr;
+    double* ipart = nullptr;
+    double* Vinv = nullptr;
+    double* fitd = nullptr;
+    int32_t* status = nullptr;
+    int32_t* status_host = nullptr;
+    hipEvent_t status_event = nullptr;
+    bool status_pending = false;
+    std::vector<void*> ws_allocs;
+};
+
+namespace {
+
+template <typename T>
+spt_status dalloc(spt_tensor_s* t, T** p, size_t count, std::vector<void*>* list) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    list->push_back(*p);
+    t->device_bytes += (int64_t)(count * sizeof(T));
+    return SPT_OK;
+}
+
+template <typename T>
+spt_status upload(spt_tensor_s* t, T** p, const std::vector<T>& v, hipStream_t s) {
+    spt_status st = dalloc(t, p, v.size(), &t->allocs);
+    if (st != SPT_OK) return st;
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return SPT_OK;
+}
+
+void release(spt_tensor_s* t) {
+    for (void* p : t->allocs) (void)hipFree(p);
+    for (void* p : t->ws_allocs) (void)hipFree(p);
+    if (t->status_host) (void)hipHostFree(t->status_host);
+    if (t->status_event) (void)hipEventDestroy(t->status_event);
+    t->allocs.clear();
+    t->ws_allocs.clear();
+}
+
+spt_status get_opts(const spt_opts* o, PlanOptions* po, int* copies) {
+    *copies = 0;
+    if (!o) return SPT_OK;
+    for (int k = 0; k < 4; ++k)
+        if (o->reserved[k] != 0) return fail(SPT_ERR_INVALID_ARG, "opts.reserved must be zero");
+    if (o->kappa < 0) return fail(SPT_ERR_INVALID_ARG, "opts.kappa must be >= 0");
+    if (o->copies != 0 && o->copies != 1) return fail(SPT_ERR_INVALID_ARG, "opts.copies must be 0 or 1");
+    if (o->split_cap < -1) return fail(SPT_ERR_INVALID_ARG, "opts.split_cap must be >= -1");
+    po->kappa = o->kappa;
+    po->split_cap = o->split_cap;
+    *copies = o->copies;
+    return SPT_OK;
+}
+
+spt_status ensure_carry(spt_tensor_s* t, int rank) {
+    if (t->ws_rank == rank) return SPT_OK;
+    for (void* p : t->ws_allocs) (void)hipFree(p);
+    t->ws_allocs.clear();
+    t->ws_rank = 0;
+    int64_t maxslots = 1, maxrows = 1;
+    for (int d = 0; d < t->N; ++d) {
+        maxslots = std::max<int64_t>(maxslots, t->nslots[d]);
+        maxrows = std::max<int64_t>(maxrows, t->dims[d]);
+    }
+    spt_status st;
+    if ((st = dalloc(t, &t->carry, (size_t)(maxslots * rank), &t->ws_allocs)) != SPT_OK) return st;
+    if (als_rank(rank)) {
+        const int64_t E = (int64_t)rank * rank;
+        const int64_t nb = std::max<int64_t>(spt::solve_blocks(maxrows), spt::gram_blocks(maxrows));
+        if ((st = dalloc(t, &t->M, (size_t)(maxrows * rank), &t->ws_allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->grams, (size_t)(t->N * E), &t->ws_allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->gpart, (size_t)(nb * E), &t->ws_allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->ipart, (size_t)(nb * rank), &t->ws_allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->Vinv, (size_t)E, &t->ws_allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->fitd, 1, &t->ws_allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->status, 1, &t->ws_allocs)) != SPT_OK) return st;
+        HIPCHK(hipMemset(t->status, 0, sizeof(int32_t)));
+    }
+    t->ws_rank = rank;
+    return SPT_OK;
+}
+
+// mode d's stream buffer and, when remapping, the target buffer
+spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int rank, float* out,
+                      bool fuse, hipStream_t s) {
+    spt_status st = ensure_carry(t, rank);
+    if (st != SPT_OK) return st;
+    const int N = t->N;
+    spt::EcArgs a{};
+    if (t->copies) {
+        a.rec_in = t->rec_mode[mode];
+        a.rec_out = nullptr;
+        a.nxt = nullptr;
+    } else {
+        a.rec_in = t->rec[t->cur];
+        a.rec_out = fuse ? t->rec[1 - t->cur] : nullptr;
+        a.nxt = fuse ? t->nxt[mode] : nullptr;
+    }
+    a.ptr = t->ptr[mode];
+    a.psplit_ptr = t->psplit_ptr[mode];
+    a.psplit_row = t->psplit_row[mode];
+    a.psplit_slot = t->psplit_slot[mode];
+    a.out = out;
+    a.carry = t->carry;
+    for (int k = 0; k < N; ++k) {
+        const int w = (mode + k) % N;
+        a.fac[k] = (const float*)factors[w];
+        a.fword[k] = t->lay.off[w] >> 5;
+        a.fshift[k] = t->lay.off[w] & 31;
+        a.fmask[k] = (uint32_t)((uint64_t(1) << t->lay.bits[w]) - 1);
+    }
+    if (!spt::launch_ec(N, rank, t->lay.words, t->kappa, a, s))
+        return fail(SPT_ERR_UNSUPPORTED, "no kernel compiled for this mode count / rank / record size");
+    HIPCHK(hipGetLastError());
+    spt::FixupArgs f{};
+    f.out = out;
+    f.carry = t->carry;
+    f.split_row = t->split_row[mode];
+    f.split_ptr = t->split_ptr[mode];
+    f.empty_rows = t->empty_rows[mode];
+    f.nsplit = t->nsplit[mode];
+    f.nempty = t->nempty[mode];
+    spt::launch_fixup(rank, f, s);
+    HIPCHK(hipGetLastError());
+    if (fuse && !t->copies) {
+        t->cur = 1 - t->cur;
+        t->cur_mode = (mode + 1) % N;
+    }
+    return SPT_OK;
+}
+
+spt_status do_remap(spt_tensor_s* t, int mode, hipStream_t s) {
+    if (t->copies) {
+        t->cur_mode = mode;
+        return SPT_OK;
+    }
+    const int N = t->N;
+    const int hops = (mode - t->cur_mode + N) % N;
+    if (hops == 0) return SPT_OK;
+    const int32_t* chain[8];
+    for (int h = 0; h < hops; ++h) chain[h] = t->nxt[(t->cur_mode + h) % N];
+    spt::launch_remap(t->lay.words, t->nnz, t->rec[t->cur], t->rec[1 - t->cur], chain, hops, s);
+    HIPCHK(hipGetLastError());
+    t->cur = 1 - t->cur;
+    t->cur_mode = mode;
+    return SPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spt_status_str(spt_status s) {
+    switch (s) {
+        case SPT_OK: return "SPT_OK";
+        case SPT_ERR_INVALID_ARG: return "SPT_ERR_INVALID_ARG";
+        case SPT_ERR_OUT_OF_RANGE: return "SPT_ERR_OUT_OF_RANGE";
+        case SPT_ERR_OOM: return "SPT_ERR_OOM";
+        case SPT_ERR_HIP: return "SPT_ERR_HIP";
+        case SPT_ERR_STATE: return "SPT_ERR_STATE";
+        case SPT_ERR_NOT_SPD: return "SPT_ERR_NOT_SPD";
+        case SPT_ERR_UNSUPPORTED: return "SPT_ERR_UNSUPPORTED";
+    }
+    return "SPT_UNKNOWN";
+}
+
+const char* spt_last_error(void) { return g_last_error.c_str(); }
+
+spt_status spt_plan_coo(int32_t nmodes, const int64_t* dims, int64_t nnz, const int32_t* indices,
+                        const spt_opts* opts, int32_t* part, int64_t* remap, int64_t* ptr,
+                        int32_t* kappa_out) {
+    g_last_error.clear();
+    PlanOptions po;
+    int copies = 0;
+    spt_status st = get_opts(opts, &po, &copies);
+    if (st != SPT_OK) return st;
+    bool range = false;
+    std::string msg = spt::validate(nmodes, dims, nnz, indices, &range);
+    if (!msg.empty()) return fail(range ? SPT_ERR_OUT_OF_RANGE : SPT_ERR_INVALID_ARG, msg);
+    po.remap_ids = remap != nullptr;
+    po.norm = false;
+    try {
+        Plan plan;
+        spt::build_plan(nmodes, dims, nnz, indices, nullptr, po, &plan);
+        for (int d = 0; d < nmodes; ++d) {
+            const auto& mp = plan.mode[d];
+            if (part) std::memcpy(part + (int64_t)d * nnz, mp.part.data(), sizeof(int32_t) * nnz);
+            if (remap)
+                for (int64_t e = 0; e < nnz; ++e) remap[(int64_t)d * nnz + e] = mp.remap[e];
+            if (ptr)
+                std::memcpy(ptr + (int64_t)d * (plan.kappa + 1), mp.ptr.data(),
+                            sizeof(int64_t) * (plan.kappa + 1));
+        }
+        if (kappa_out) *kappa_out = plan.kappa;
+    } catch (const std::bad_alloc&) {
+        return fail(SPT_ERR_OOM, "host allocation failed in the planner");
+    }
+    return SPT_OK;
+}
+
+spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
+                               const int32_t* indices, const float* values, const spt_opts* opts,
+                               void* stream, spt_tensor_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(SPT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    PlanOptions po;
+    int copies = 0;
+    spt_status st = get_opts(opts, &po, &copies);
+    if (st != SPT_OK) return st;
+    bool range = false;
+    std::string msg = spt::validate(nmodes, dims, nnz, indices, &range);
+    if (!msg.empty()) return fail(range ? SPT_ERR_OUT_OF_RANGE : SPT_ERR_INVALID_ARG, msg);
+    if (nnz > 0 && !values) return fail(SPT_ERR_INVALID_ARG, "values is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    spt_tensor_s* t = nullptr;
+    try {
+        t = new spt_tensor_s();
+        t->N = nmodes;
+        t->nnz = nnz;
+        for (int w = 0; w < nmodes; ++w) t->dims[w] = dims[w];
+        t->copies = copies;
+        if (!spt::choose_layout(nmodes, dims, &t->lay)) {
+            delete t;
+            return fail(SPT_ERR_UNSUPPORTED, "index bits exceed a 32-byte record");
+        }
+        Plan plan;
+        spt::build_plan(nmodes, dims, nnz, indices, values, po, &plan);
+        t->kappa = plan.kappa;
+        t->norm_sq = plan.norm_sq;
+        const int W = t->lay.words;
+        auto pack_stream = [&](const std::vector<int32_t>& order, std::vector<uint32_t>& recs) {
+            recs.resize((size_t)nnz * W);
+            for (int64_t p = 0; p < nnz; ++p)
+                spt::pack_record(t->lay, indices, nnz, values, order[p], &recs[(size_t)p * W]);
+        };
+        std::vector<uint32_t> recs;
+        std::vector<int32_t> nxt;
+        for (int d = 0; d < nmodes; ++d) {
+            const auto& mp = plan.mode[d];
+            t->nsplit[d] = (int32_t)mp.split_row.size();
+            t->nslots[d] = (int32_t)mp.slot_part.size();
+            t->nempty[d] = (int32_t)mp.empty_rows.size();
+            t->max_load[d] = mp.max_load;
+            if ((st = upload(t, &t->ptr[d], mp.ptr, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->psplit_ptr[d], mp.psplit_ptr, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->psplit_row[d], mp.psplit_row, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->psplit_slot[d], mp.psplit_slot, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->split_row[d], mp.split_row, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->split_ptr[d], mp.split_ptr, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->empty_rows[d], mp.empty_rows, s)) != SPT_OK) break;
+            if (copies) {
+                pack_stream(mp.order, recs);
+                if ((st = upload(t, &t->rec_mode[d], recs, s)) != SPT_OK) break;
+            } else {
+                const auto& nx = plan.mode[(d + 1) % nmodes].remap;
+                nxt.resize(nnz);
+                for (int64_t p = 0; p < nnz; ++p) nxt[p] = nx[mp.order[p]];
+                if ((st = upload(t, &t->nxt[d], nxt, s)) != SPT_OK) break;
+            }
+            // the uploads above read host vectors that are reused next mode
+            if (hipStreamSynchronize(s) != hipSuccess) {
+                st = fail(SPT_ERR_HIP, "hipStreamSynchronize after upload");
+                break;
+            }
+        }
+        if (st == SPT_OK && !copies) {
+            pack_stream(plan.mode[0].order, recs);
+            if ((st = upload(t, &t->rec[0], recs, s)) == SPT_OK)
+                st = dalloc(t, &t->rec[1], recs.size(), &t->allocs);
+        }
+        if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess)
+            st = fail(SPT_ERR_HIP, "hipStreamSynchronize after upload");
+        if (st != SPT_OK) {
+            release(t);
+            delete t;
+            return st;
+        }
+        t->order0 = plan.mode[0].order;
+        t->cur = 0;
+        t->cur_mode = 0;
+    } catch (const std::bad_alloc&) {
+        if (t) {
+            release(t);
+            delete t;
+        }
+        return fail(SPT_ERR_OOM, "host allocation failed during preprocessing");
+    }
+    t->prep_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = t;
+    return SPT_OK;
+}
+
+spt_status spt_tensor_free(spt_tensor_t t) {
+    g_last_error.clear();
+    if (!t) return SPT_OK;
+    release(t);
+    delete t;
+    return SPT_OK;
+}
+
+spt_status spt_tensor_info(spt_tensor_t t, spt_info* info) {
+    g_last_error.clear();
+    if (!t || !info) return fail(SPT_ERR_INVALID_ARG, "NULL handle or info");
+    std::memset(info, 0, sizeof(*info));
+    info->nmodes = t->N;
+    info->cur_mode = t->cur_mode;
+    info->kappa = t->kappa;
+    info->record_bytes = t->lay.words * 4;
+    info->nnz = t->nnz;
+    for (int w = 0; w < t->N; ++w) {
+        info->dims[w] = t->dims[w];
+        info->max_load[w] = t->max_load[w];
+        info->split_rows[w] = t->nsplit[w];
+    }
+    info->norm_sq = t->norm_sq;
+    info->prep_seconds = t->prep_seconds;
+    info->device_bytes = t->device_bytes;
+    return SPT_OK;
+}
+
+spt_status spt_remap_for_mode(spt_tensor_t t, int32_t mode, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
+    if (mode < 0 || mode >= t->N) return fail(SPT_ERR_INVALID_ARG, "mode out of range");
+    return do_remap(t, mode, (hipStream_t)stream);
+}
+
+spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void* const* factors, spt_dtype fdtype,
+                      int32_t rank, float* out, uint32_t flags, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
+    if (mode < 0 || mode >= t->N) return fail(SPT_ERR_INVALID_ARG, "mode out of range");
+    if (fdtype != SPT_F32) return fail(SPT_ERR_UNSUPPORTED, "factor dtype not supported");
+    if (!rank_compiled(rank)) return fail(SPT_ERR_UNSUPPORTED, "rank must be 8, 16, 32, 64 or 128");
+    if (!factors || !out) return fail(SPT_ERR_INVALID_ARG, "NULL factors or out");
+    for (int w = 0; w < t->N; ++w)
+        if (w != mode && !factors[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor matrix");
+    if (flags & ~(SPT_FUSE_REMAP_NEXT | SPT_AUTO_REMAP)) return fail(SPT_ERR_INVALID_ARG, "unknown flag");
+    hipStream_t s = (hipStream_t)stream;
+    if (!t->copies && t->cur_mode != mode) {
+        if (!(flags & SPT_AUTO_REMAP))
+            return fail(SPT_ERR_STATE, "stream is in mode " + std::to_string(t->cur_mode) +
+                                           "'s order, not " + std::to_string(mode) + "'s");
+        spt_status st = do_remap(t, mode, s);
+        if (st != SPT_OK) return st;
+    }
+    return run_mttkrp(t, mode, factors, rank, out, (flags & SPT_FUSE_REMAP_NEXT) != 0, s);
+}
+
+spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtype, int32_t rank,
+                           double* lambda, double* fit, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
+    if (fdtype != SPT_F32) return fail(SPT_ERR_UNSUPPORTED, "factor dtype not supported");
+    if (!als_rank(rank)) return fail(SPT_ERR_UNSUPPORTED, "CP-ALS rank must be 8, 16, 32 or 64");
+    if (!factors || !lambda) return fail(SPT_ERR_INVALID_ARG, "NULL factors or lambda");
+    for (int w = 0; w < t->N; ++w)
+        if (!factors[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor matrix");
+    if (!t->copies && t->cur_mode != 0) return fail(SPT_ERR_STATE, "stream must be in mode 0's order");
+    if (fit && t->norm_sq <= 0.0) return fail(SPT_ERR_INVALID_ARG, "fit undefined for a zero tensor");
+    hipStream_t s = (hipStream_t)stream;
+    // a failure flagged by an earlier sweep that was not synchronised
+    if (t->status_pending) {
+        HIPCHK(hipEventSynchronize(t->status_event));
+        t->status_pending = false;
+        if (t->status_host[0] != 0) {
+            t->status_host[0] = 0;
+            return fail(SPT_ERR_NOT_SPD, "normal matrix not positive definite (earlier sweep)");
+        }
+    }
+    spt_status st = ensure_carry(t, rank);
+    if (st != SPT_OK) return st;
+    if (!t->status_host) {
+        HIPCHK(hipHostMalloc((void**)&t->status_host, sizeof(int32_t)));
+        t->status_host[0] = 0;
+        HIPCHK(hipEventCreateWithFlags(&t->status_event, hipEventDisableTiming));
+    }
+    const int N = t->N;
+    const int64_t E = (int64_t)rank * rank;
+    for (int w = 1; w < N; ++w) {
+        const int nb = spt::gram_blocks(t->dims[w]);
+        spt::launch_gram_partial(rank, (const float*)factors[w], t->dims[w], t->gpart, s);
+        spt::launch_gram_reduce(rank, t->gpart, nb, t->grams + w * E, s);
+    }
+    HIPCHK(hipGetLastError());
+    for (int d = 0; d < N; ++d) {
+        st = run_mttkrp(t, d, (const void* const*)factors, rank, t->M, true, s);
+        if (st != SPT_OK) return st;
+        spt::launch_normal_inverse(rank, N, d, t->grams, t->Vinv, t->status, s);
+        const int nb = spt::solve_blocks(t->dims[d]);
+        spt::launch_solve_rows(rank, t->M, t->Vinv, t->dims[d], (float*)factors[d], t->gpart,
+                               t->ipart, s);
+        spt::launch_als_finish(rank, N, d, t->gpart, t->ipart, nb, t->grams, lambda, t->norm_sq,
+                               (fit && d == N - 1) ? 1 : 0, t->fitd, s);
+        spt::launch_scale_cols(rank, (float*)factors[d], t->dims[d], lambda, s);
+        HIPCHK(hipGetLastError());
+    }
+    if (t->copies) t->cur_mode = 0;
+    HIPCHK(hipMemcpyAsync(t->status_host, t->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    spt::launch_zero_i32(t->status, 1, s);
+    HIPCHK(hipEventRecord(t->status_event, s));
+    t->status_pending = true;
+    if (fit) {
+        HIPCHK(hipMemcpyAsync(fit, t->fitd, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        t->status_pending = false;
+        if (t->status_host[0] != 0) {
+            t->status_host[0] = 0;
+            return fail(SPT_ERR_NOT_SPD, "normal matrix not positive definite");
+        }
+    }
+    return SPT_OK;
+}
+
+spt_status spt_tensor_get_remap(spt_tensor_t t, int32_t mode, int64_t* b_host) {
+    g_last_error.clear();
+    if (!t || !b_host) return fail(SPT_ERR_INVALID_ARG, "NULL handle or output");
+    if (mode < 0 || mode >= t->N) return fail(SPT_ERR_INVALID_ARG, "mode out of range");
+    if (t->copies) return fail(SPT_ERR_UNSUPPORTED, "no remap ids are held with one copy per mode");
+    const int64_t nnz = t->nnz;
+    try {
+        // b_0 from the mode-0 stream, then follow the device's next-position
+        // arrays mode by mode
+        std::vector<int32_t> pos(nnz), nx(nnz);
+        for (int64_t p = 0; p < nnz; ++p) pos[t->order0[p]] = (int32_t)p;
+        for (int d = 0; d < mode; ++d) {
+            if (nnz) HIPCHK(hipMemcpy(nx.data(), t->nxt[d], sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+            for (int64_t e = 0; e < nnz; ++e) pos[e] = nx[pos[e]];
+        }
+        for (int64_t e = 0; e < nnz; ++e) b_host[e] = pos[e];
+    } catch (const std::bad_alloc&) {
+        return fail(SPT_ERR_OOM, "host allocation failed");
+    }
+    return SPT_OK;
+}
+
+spt_status spt_tensor_get_records(spt_tensor_t t, int32_t* idx_host, float* val_host,
+                                  int32_t* cur_mode) {
+    g_last_error.clear();
+    if (!t || !idx_host || !val_host) return fail(SPT_ERR_INVALID_ARG, "NULL handle or output");
+    const int64_t nnz = t->nnz;
+    const int W = t->lay.words;
+    const uint32_t* src = t->copies ? t->rec_mode[t->cur_mode] : t->rec[t->cur];
+    try {
+        std::vector<uint32_t> recs((size_t)nnz * W);
+        HIPCHK(hipDeviceSynchronize());
+        if (nnz) HIPCHK(hipMemcpy(recs.data(), src, recs.size() * 4, hipMemcpyDeviceToHost));
+        int32_t c[8];
+        for (int64_t p = 0; p < nnz; ++p) {
+            spt::unpack_record(t->lay, &recs[(size_t)p * W], c, &val_host[p]);
+            for (int w = 0; w < t->N; ++w) idx_host[(int64_t)w * nnz + p] = c[w];
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(SPT_ERR_OOM, "host allocation failed");
+    }
+    if (cur_mode) *cur_mode = t->cur_mode;
+    return SPT_OK;
+}
+
+}  // extern "C"

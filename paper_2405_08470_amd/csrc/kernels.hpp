@@ -1,0 +1,70 @@
+// Launch interface of the gfx950 kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spt {
+
+// Arguments of the fused elementwise-computation / remapping kernel for one
+// output mode d.  Everything "rotated" is indexed k = 0..N-1 for mode
+// (d + k) mod N, so k = 0 is the output mode.
+struct EcArgs {
+    const uint32_t* rec_in;    // packed records of mode d's stream
+    uint32_t* rec_out;         // remap target in mode d+1's order, or nullptr
+    const int32_t* nxt;        // [nnz] position in mode d+1 of the record at p
+    const int64_t* ptr;        // [kappa+1] partition offsets of mode d
+    const int32_t* psplit_ptr; // [kappa+1] split rows of each partition
+    const int32_t* psplit_row;
+    const int32_t* psplit_slot;
+    float* out;                // I_d x R
+    float* carry;              // nslots x R partial sums of split rows
+    const float* fac[8];       // rotated factor matrices (fac[0] unused)
+    int32_t fword[8];          // rotated field: first word,
+    int32_t fshift[8];         //   bit shift within it,
+    uint32_t fmask[8];         //   and width mask
+};
+
+struct FixupArgs {
+    float* out;
+    const float* carry;
+    const int32_t* split_row;  // [nsplit]
+    const int32_t* split_ptr;  // [nsplit+1]
+    const int32_t* empty_rows; // [nempty]
+    int32_t nsplit;
+    int32_t nempty;
+};
+
+// Returns false if (nmodes, rank, words) has no compiled kernel.
+bool launch_ec(int nmodes, int rank, int words, int kappa, const EcArgs& a, hipStream_t s);
+void launch_fixup(int rank, const FixupArgs& a, hipStream_t s);
+// Moves every record of the stream from position p to the position reached by
+// following `hops` next-position arrays (nxt[0] first).
+void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,
+                  const int32_t* const* nxt, int hops, hipStream_t s);
+
+// ---- CP-ALS dense step (FP64 for everything R x R) ----
+int gram_blocks(int64_t rows);
+// partial[b][R*R] for b < gram_blocks(rows)
+void launch_gram_partial(int rank, const float* Y, int64_t rows, double* partial, hipStream_t s);
+// G = sum of partials; G is R x R
+void launch_gram_reduce(int rank, const double* partial, int nblocks, double* G, hipStream_t s);
+// V = Hadamard of grams[w] (w != mode); Cholesky; Vinv.  status[0] |= 1 on
+// failure after one ridge retry.
+void launch_normal_inverse(int rank, int nmodes, int mode, const double* grams, double* Vinv,
+                           int32_t* status, hipStream_t s);
+// Y = M Vinv (FP32 out); partial Grams of Y and partial column sums of M.*Y
+int solve_blocks(int64_t rows);
+void launch_solve_rows(int rank, const float* M, const double* Vinv, int64_t rows, float* Y,
+                       double* gpart, double* ipart, hipStream_t s);
+// From the partials: G_un, lambda = sqrt(diag), G_mode = D^-1 G_un D^-1,
+// inner_r; if want_fit, fit[0] from all grams, lambda and normX2.
+void launch_als_finish(int rank, int nmodes, int mode, const double* gpart, const double* ipart,
+                       int nblocks, double* grams, double* lambda, double normX2, int want_fit,
+                       double* fit, hipStream_t s);
+void launch_scale_cols(int rank, float* Y, int64_t rows, const double* lambda, hipStream_t s);
+// p[0..n) = 0 with a kernel (no memset node when a caller captures a graph)
+void launch_zero_i32(int32_t* p, int n, hipStream_t s);
+
+}  // namespace spt

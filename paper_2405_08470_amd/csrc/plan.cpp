@@ -1,0 +1,293 @@
+// Host-side preprocessing: Algorithm 1 (Sec. 3.4) with the piece split of
+// heavy rows, remap ids, record packing and the tables the kernels use.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <queue>
+#include <utility>
+
+namespace spt {
+
+namespace {
+
+int bit_length(int64_t v) {
+    int b = 0;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+// Stable counting sort of `in` (a permutation of nonzeros) by key[e] in
+// [0, nkeys); result in `out`.  `count` is scratch of size nkeys + 1.
+void counting_sort(const std::vector<int32_t>& in, const int32_t* key, int64_t nkeys,
+                   std::vector<int32_t>& out, std::vector<int64_t>& count) {
+    count.assign(nkeys + 1, 0);
+    const int64_t n = (int64_t)in.size();
+    for (int64_t p = 0; p < n; ++p) ++count[key[in[p]] + 1];
+    for (int64_t k = 0; k < nkeys; ++k) count[k + 1] += count[k];
+    out.resize(n);
+    for (int64_t p = 0; p < n; ++p) out[count[key[in[p]]]++] = in[p];
+}
+
+struct Item {
+    int64_t size;
+    int32_t row;
+    int32_t piece;
+};
+
+}  // namespace
+
+int32_t default_kappa(int64_t nnz) {
+    int64_t k = (nnz + 2047) / 2048;
+    return (int32_t)std::min<int64_t>(16384, std::max<int64_t>(1, k));
+}
+
+std::string validate(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                     bool* range_error) {
+    *range_error = false;
+    if (nmodes < 2 || nmodes > kMaxModes) return "nmodes must be in [2, 8]";
+    if (!dims) return "dims is NULL";
+    for (int w = 0; w < nmodes; ++w) {
+        if (dims[w] < 1 || dims[w] >= (int64_t(1) << 31)) {
+            *range_error = true;
+            return "dims[" + std::to_string(w) + "] = " + std::to_string(dims[w]) +
+                   " is outside [1, 2^31)";
+        }
+    }
+    if (nnz < 0 || nnz >= (int64_t(1) << 31)) {
+        *range_error = true;
+        return "nnz = " + std::to_string(nnz) + " is outside [0, 2^31)";
+    }
+    if (nnz > 0 && !idx) return "indices is NULL";
+    for (int w = 0; w < nmodes; ++w) {
+        const int32_t* c = idx + (int64_t)w * nnz;
+        const int64_t I = dims[w];
+        for (int64_t e = 0; e < nnz; ++e) {
+            if (c[e] < 0 || c[e] >= I) {
+                *range_error = true;
+                return "index " + std::to_string(c[e]) + " of nonzero " + std::to_string(e) +
+                       " is outside mode " + std::to_string(w) + " (size " + std::to_string(I) +
+                       ")";
+            }
+        }
+    }
+    return "";
+}
+
+bool choose_layout(int nmodes, const int64_t* dims, RecordLayout* lay) {
+    lay->nmodes = nmodes;
+    int total = 0;
+    for (int w = 0; w < nmodes; ++w) {
+        int b = std::max(1, bit_length(dims[w] - 1));
+        lay->bits[w] = b;
+        lay->off[w] = total;
+        total += b;
+    }
+    if (total <= 96)
+        lay->words = 4;
+    else if (total <= 224)
+        lay->words = 8;
+    else
+        return false;
+    return true;
+}
+
+void pack_record(const RecordLayout& lay, const int32_t* idx, int64_t nnz, const float* val,
+                 int64_t e, uint32_t* out) {
+    for (int k = 0; k < lay.words; ++k) out[k] = 0;
+    for (int w = 0; w < lay.nmodes; ++w) {
+        uint32_t v = (uint32_t)idx[(int64_t)w * nnz + e];
+        int o = lay.off[w];
+        int wi = o >> 5, sh = o & 31;
+        out[wi] |= v << sh;
+        if (sh + lay.bits[w] > 32) out[wi + 1] |= v >> (32 - sh);
+    }
+    float f = val ? val[e] : 0.0f;
+    std::memcpy(&out[lay.words - 1], &f, 4);
+}
+
+void unpack_record(const RecordLayout& lay, const uint32_t* rec, int32_t* c, float* v) {
+    for (int w = 0; w < lay.nmodes; ++w) {
+        int o = lay.off[w];
+        int wi = o >> 5, sh = o & 31;
+        uint64_t lo = rec[wi];
+        uint64_t hi = (wi + 1 < lay.words - 1) ? rec[wi + 1] : 0;
+        uint64_t x = ((hi << 32) | lo) >> sh;
+        c[w] = (int32_t)(x & ((uint64_t(1) << lay.bits[w]) - 1));
+    }
+    std::memcpy(v, &rec[lay.words - 1], 4);
+}
+
+void build_plan(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                const float* val, const PlanOptions& opt, Plan* plan) {
+    const int N = nmodes;
+    plan->nmodes = N;
+    plan->nnz = nnz;
+    plan->dims.assign(dims, dims + N);
+    plan->kappa = opt.kappa > 0 ? opt.kappa : default_kappa(nnz);
+    const int32_t kappa = plan->kappa;
+    int64_t cap;
+    if (opt.split_cap < 0)
+        cap = 0;  // never split
+    else if (opt.split_cap == 0)
+        cap = std::max<int64_t>(1, (nnz + kappa - 1) / kappa);
+    else
+        cap = opt.split_cap;
+    plan->cap = cap;
+
+    std::vector<int64_t> count;
+    for (int d = 0; d < N; ++d) {
+        ModePlan& mp = plan->mode[d];
+        const int64_t I = dims[d];
+        const int32_t* c = idx + (int64_t)d * nnz;
+        // degree of every vertex of mode d
+        std::vector<int64_t> deg(I, 0);
+        for (int64_t e = 0; e < nnz; ++e) ++deg[c[e]];
+        // items: each vertex, or its pieces when heavier than cap
+        std::vector<int64_t> piece_base(I + 1, 0);
+        for (int64_t i = 0; i < I; ++i) {
+            int64_t k = (cap > 0 && deg[i] > cap) ? (deg[i] + cap - 1) / cap : 1;
+            piece_base[i + 1] = piece_base[i] + k;
+        }
+        const int64_t nitems = piece_base[I];
+        std::vector<Item> items(nitems);
+        for (int64_t i = 0; i < I; ++i) {
+            int64_t k = piece_base[i + 1] - piece_base[i];
+            int64_t q = deg[i] / k, rem = deg[i] % k;
+            for (int64_t j = 0; j < k; ++j)
+                items[piece_base[i] + j] = Item{q + (j < rem ? 1 : 0), (int32_t)i, (int32_t)j};
+        }
+        // decreasing size, then row, then piece
+        std::sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+            if (a.size != b.size) return a.size > b.size;
+            if (a.row != b.row) return a.row < b.row;
+            return a.piece < b.piece;
+        });
+        // least-filled block first, ties to the lowest block id: a min-heap
+        // on (load, id)
+        using LoadId = std::pair<int64_t, int32_t>;
+        std::priority_queue<LoadId, std::vector<LoadId>, std::greater<LoadId>> heap;
+        for (int32_t z = 0; z < kappa; ++z) heap.push(LoadId(0, z));
+        std::vector<int32_t> piece_part(nitems);
+        mp.loads.assign(kappa, 0);
+        for (const Item& it : items) {
+            LoadId top = heap.top();
+            heap.pop();
+            piece_part[piece_base[it.row] + it.piece] = top.second;
+            top.first += it.size;
+            mp.loads[top.second] = top.first;
+            heap.push(top);
+        }
+        items.clear();
+        items.shrink_to_fit();
+        mp.ptr.assign(kappa + 1, 0);
+        for (int32_t z = 0; z < kappa; ++z) mp.ptr[z + 1] = mp.ptr[z] + mp.loads[z];
+        mp.max_load = *std::max_element(mp.loads.begin(), mp.loads.end());
+        // partition of every nonzero: its row's piece, pieces taking the
+        // row's nonzeros in input order
+        mp.part.resize(nnz);
+        std::vector<int64_t> seen(I, 0);
+        for (int64_t e = 0; e < nnz; ++e) {
+            const int32_t i = c[e];
+            const int64_t k = piece_base[i + 1] - piece_base[i];
+            int64_t j = 0;
+            if (k > 1) {
+                const int64_t rank = seen[i]++;
+                const int64_t q = deg[i] / k, rem = deg[i] % k, big = rem * (q + 1);
+                j = rank < big ? rank / (q + 1) : rem + (rank - big) / q;
+            }
+            mp.part[e] = piece_part[piece_base[i] + j];
+        }
+        // split rows: pieces in two or more partitions
+        mp.split_row.clear();
+        mp.split_ptr.assign(1, 0);
+        mp.slot_part.clear();
+        std::vector<std::vector<std::pair<int32_t, int32_t>>> per_part(kappa);
+        std::vector<int32_t> parts;
+        for (int64_t i = 0; i < I; ++i) {
+            const int64_t k = piece_base[i + 1] - piece_base[i];
+            if (k < 2) continue;
+            parts.assign(piece_part.begin() + piece_base[i], piece_part.begin() + piece_base[i + 1]);
+            std::sort(parts.begin(), parts.end());
+            parts.erase(std::unique(parts.begin(), parts.end()), parts.end());
+            if (parts.size() < 2) continue;
+            mp.split_row.push_back((int32_t)i);
+            for (int32_t z : parts) {
+                int32_t slot = (int32_t)mp.slot_part.size();
+                mp.slot_part.push_back(z);
+                per_part[z].push_back({(int32_t)i, slot});
+            }
+            mp.split_ptr.push_back((int32_t)mp.slot_part.size());
+        }
+        mp.psplit_ptr.assign(kappa + 1, 0);
+        mp.psplit_row.clear();
+        mp.psplit_slot.clear();
+        for (int32_t z = 0; z < kappa; ++z) {
+            for (auto& rs : per_part[z]) {
+                mp.psplit_row.push_back(rs.first);
+                mp.psplit_slot.push_back(rs.second);
+            }
+            mp.psplit_ptr[z + 1] = (int32_t)mp.psplit_row.size();
+        }
+        mp.empty_rows.clear();
+        for (int64_t i = 0; i < I; ++i)
+            if (deg[i] == 0) mp.empty_rows.push_back((int32_t)i);
+    }
+
+    if (opt.remap_ids) {
+        // Stream of mode d: sorted by (z_d, c_d, z_{d-1}, c_{d-1}, ...,
+        // z_{d+1}, c_{d+1}, e).  Built least significant key first by stable
+        // sorts on the pair (z_w, c_w) for w = 1, 2, ..., N-1, 0; afterwards
+        // each further stable sort by (z_d, c_d) yields mode d's stream.
+        std::vector<int32_t> order(nnz), tmp;
+        for (int64_t e = 0; e < nnz; ++e) order[e] = (int32_t)e;
+        auto sort_pair = [&](int w) {
+            counting_sort(order, idx + (int64_t)w * nnz, dims[w], tmp, count);
+            counting_sort(tmp, plan->mode[w].part.data(), kappa, order, count);
+        };
+        for (int k = 1; k <= N; ++k) sort_pair(k % N);
+        for (int d = 0; d < N; ++d) {
+            if (d > 0) sort_pair(d);
+            ModePlan& mp = plan->mode[d];
+            mp.order = order;
+            mp.remap.resize(nnz);
+            for (int64_t p = 0; p < nnz; ++p) mp.remap[order[p]] = (int32_t)p;
+        }
+    }
+
+    if (opt.norm) {
+        // ||X||^2 with repeated coordinates summed first: sort by the full
+        // coordinate (stable passes over modes N-1 .. 0), then FP64 sums of
+        // each run in input order.
+        std::vector<int32_t> order(nnz), tmp;
+        for (int64_t e = 0; e < nnz; ++e) order[e] = (int32_t)e;
+        for (int w = N - 1; w >= 0; --w) {
+            counting_sort(order, idx + (int64_t)w * nnz, dims[w], tmp, count);
+            order.swap(tmp);
+        }
+        double total = 0.0;
+        int64_t p = 0;
+        while (p < nnz) {
+            int64_t q = p + 1;
+            auto same = [&](int64_t a, int64_t b) {
+                for (int w = 0; w < N; ++w)
+                    if (idx[(int64_t)w * nnz + a] != idx[(int64_t)w * nnz + b]) return false;
+                return true;
+            };
+            double s = val ? (double)val[order[p]] : 0.0;
+            while (q < nnz && same(order[p], order[q])) {
+                s += val ? (double)val[order[q]] : 0.0;
+                ++q;
+            }
+            total += s * s;
+            p = q;
+        }
+        plan->norm_sq = total;
+    }
+}
+
+}  // namespace spt

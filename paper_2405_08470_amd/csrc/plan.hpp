@@ -1,0 +1,79 @@
+// Host-side preprocessing of a COO tensor: per-mode partitioning (Alg. 1,
+// Sec. 3.4), remap ids (Sec. 3.4-3.5) and the packed record stream.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace spt {
+
+constexpr int kMaxModes = 8;
+
+// Bit layout of one packed record <c_0..c_{N-1}, val>: the N indices are
+// packed little-endian into the first (words-1) 32-bit words, field w
+// taking bits [off[w], off[w]+bits[w]); the last word holds the FP32 value.
+struct RecordLayout {
+    int nmodes = 0;
+    int words = 0;            // 4 (16 B) or 8 (32 B)
+    int bits[kMaxModes] = {};
+    int off[kMaxModes] = {};
+};
+
+struct ModePlan {
+    std::vector<int32_t> part;        // [nnz] partition of each nonzero (z_d)
+    std::vector<int64_t> loads;       // [kappa]
+    std::vector<int64_t> ptr;         // [kappa+1]
+    std::vector<int32_t> order;       // [nnz] nonzero at each stream position
+    std::vector<int32_t> remap;       // [nnz] b_d(e): position of e
+    // rows whose pieces landed in >= 2 partitions ("split rows"); one carry
+    // slot per (row, partition), slots ordered by (row, partition)
+    std::vector<int32_t> split_row;   // [nsplit]
+    std::vector<int32_t> split_ptr;   // [nsplit+1] slot ranges per split row
+    std::vector<int32_t> slot_part;   // [nslots]
+    // per partition: its split rows and their slots (CSR over partitions)
+    std::vector<int32_t> psplit_ptr;  // [kappa+1]
+    std::vector<int32_t> psplit_row;  // [nslots]
+    std::vector<int32_t> psplit_slot; // [nslots]
+    std::vector<int32_t> empty_rows;  // rows with no nonzero
+    int64_t max_load = 0;
+};
+
+struct Plan {
+    int nmodes = 0;
+    int64_t nnz = 0;
+    int32_t kappa = 0;
+    int64_t cap = 0;
+    std::vector<int64_t> dims;
+    ModePlan mode[kMaxModes];
+    RecordLayout layout;
+    double norm_sq = 0.0;
+};
+
+struct PlanOptions {
+    int32_t kappa = 0;       // 0 -> default_kappa(nnz)
+    int64_t split_cap = 0;   // 0 -> ceil(nnz/kappa); <0 -> never split
+    bool remap_ids = true;   // build orders / remap ids
+    bool norm = true;        // compute ||X||^2 of the coalesced tensor
+};
+
+int32_t default_kappa(int64_t nnz);
+
+// Validates the input; returns "" or a message (and sets *range_error when
+// the failure is an index or size out of range).
+std::string validate(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                     bool* range_error);
+
+// Computes the whole plan.  Throws std::bad_alloc on allocation failure.
+void build_plan(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                const float* val, const PlanOptions& opt, Plan* plan);
+
+// Chooses the record layout; returns false when the index bits exceed 224.
+bool choose_layout(int nmodes, const int64_t* dims, RecordLayout* lay);
+
+// Packs nonzero e into `words` 32-bit words.
+void pack_record(const RecordLayout& lay, const int32_t* idx, int64_t nnz, const float* val,
+                 int64_t e, uint32_t* out);
+void unpack_record(const RecordLayout& lay, const uint32_t* rec, int32_t* c, float* v);
+
+}  // namespace spt
