@@ -46,8 +46,9 @@ typedef struct spt_tensor_s *spt_tensor_t;  /* opaque, owned by the library */
 
 /* Options of spt_tensor_load_coo; NULL means all defaults. */
 typedef struct spt_opts {
-    int32_t kappa;      /* partitions per mode (kappa of Alg. 1); 0 = default:
-                           min(8 * #CUs, max(1, nnz / 1024))                  */
+    int32_t kappa;      /* partitions per mode (kappa of Alg. 1) = workgroups
+                           of each mode's kernel; 0 = default:
+                           clamp(ceil(nnz / 2048), 1, 16384)                  */
     int32_t copies;     /* 0 = one tensor copy plus its remapping target
                            (the paper's dynamic remapping); 1 = one
                            mode-ordered copy per mode, no remapping needed  */
@@ -161,6 +162,24 @@ spt_status spt_tensor_get_remap(spt_tensor_t t, int32_t mode, int64_t *b_host);
 spt_status spt_tensor_get_records(spt_tensor_t t, int32_t *idx_host, float *val_host,
                                   int32_t *cur_mode);
 
+/* Kernel time of the launches made on one tensor (spt_timing_control). */
+typedef struct spt_timing {
+    int64_t calls[8];        /* timed spMTTKRP launches per output mode        */
+    double ec_ms[8];         /* fused elementwise (+remap) kernel, summed      */
+    double fixup_ms[8];      /* split-row fixup and empty-row fill, summed     */
+    double als_ms[8];        /* CP-ALS dense step after that mode's MTTKRP     */
+} spt_timing;
+
+/*
+ * spt_timing_control -- per-kernel timing with HIP events recorded on the
+ * launch stream.  If out != NULL it first waits for the events recorded so
+ * far and fills *out (host) with their totals; then enable != 0 clears the
+ * totals and starts recording around every later launch on this tensor,
+ * enable == 0 stops recording.  Recording adds a few microseconds of host
+ * time per launch and nothing to the kernels.
+ */
+spt_status spt_timing_control(spt_tensor_t t, int32_t enable, spt_timing *out);
+
 /* spt_tensor_free -- releases the handle and its device memory (NULL ok). */
 spt_status spt_tensor_free(spt_tensor_t t);
 
@@ -172,6 +191,7 @@ spt_status spt_tensor_free(spt_tensor_t t);
  *   remap int64 [N][nnz]   remap id b_d(e) = position in mode d's stream
  *   ptr   int64 [N][kappa+1] partition offsets of each stream
  *   kappa_out              the kappa used
+ * With part, remap and ptr all NULL only kappa_out is filled (no planning).
  */
 spt_status spt_plan_coo(int32_t nmodes, const int64_t *dims, int64_t nnz,
                         const int32_t *indices, const spt_opts *opts, int32_t *part,

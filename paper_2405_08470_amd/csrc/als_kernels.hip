@@ -52,13 +52,34 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const float* __restri
     }
 }
 
-__global__ void gram_reduce_kernel(const double* __restrict__ partial, int nblocks, int E,
-                                   double* __restrict__ G) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * E + e];
-    G[e] = s;
+// out[e] = sum over b of partial[b][e] for e < E.  Each entry is summed by
+// 8 chains (b = c, c+8, ...), each with 4 interleaved accumulators, and the
+// chains are combined in a fixed order.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partial,
+                                                              int nblocks, int E,
+                                                              double* __restrict__ out) {
+    __shared__ double red[8][32];
+    const int tid = threadIdx.x;
+    const int el = tid % 32, c = tid / 32;
+    const int e = blockIdx.x * 32 + el;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (e < E) {
+        int b = c;
+        for (; b + 24 < nblocks; b += 32) {
+            s0 += partial[(int64_t)b * E + e];
+            s1 += partial[(int64_t)(b + 8) * E + e];
+            s2 += partial[(int64_t)(b + 16) * E + e];
+            s3 += partial[(int64_t)(b + 24) * E + e];
+        }
+        for (; b < nblocks; b += 8) s0 += partial[(int64_t)b * E + e];
+    }
+    red[c][el] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (tid < 32 && e < E) {
+        double t = 0.0;
+        for (int k = 0; k < 8; ++k) t += red[k][tid];
+        out[e] = t;
+    }
 }
 
 // In-place Cholesky of the R x R matrix in A (lower triangle); returns
@@ -215,31 +236,19 @@ __global__ __launch_bounds__(256) void solve_rows_kernel(const float* __restrict
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void als_finish_kernel(const double* __restrict__ gpart,
-                                                          const double* __restrict__ ipart,
-                                                          int nblocks, int nmodes, int mode,
+__global__ __launch_bounds__(256) void als_finish_kernel(const double* __restrict__ Gun,
+                                                          const double* __restrict__ Isum,
+                                                          int nmodes, int mode,
                                                           double* __restrict__ grams,
                                                           double* __restrict__ lambda,
                                                           double normX2, int want_fit,
                                                           double* __restrict__ fit) {
     constexpr int E = R * R;
-    __shared__ double G[R][R];
     __shared__ double lam[R];
-    __shared__ double inner[R];
+    __shared__ double red[256];
     const int tid = threadIdx.x;
-    for (int e = tid; e < E; e += 256) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += gpart[(int64_t)b * E + e];
-        G[e / R][e % R] = s;
-    }
     if (tid < R) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += ipart[(int64_t)b * R + tid];
-        inner[tid] = s;
-    }
-    __syncthreads();
-    if (tid < R) {
-        lam[tid] = sqrt(G[tid][tid]);
+        lam[tid] = sqrt(Gun[tid * R + tid]);
         lambda[tid] = lam[tid];
     }
     __syncthreads();
@@ -247,21 +256,26 @@ __global__ __launch_bounds__(256) void als_finish_kernel(const double* __restric
     for (int e = tid; e < E; e += 256) {
         const int r = e / R, c = e % R;
         const double lr = lam[r], lc = lam[c];
-        Gm[e] = (lr > 0.0 && lc > 0.0) ? G[r][c] / (lr * lc) : 0.0;
+        Gm[e] = (lr > 0.0 && lc > 0.0) ? Gun[e] / (lr * lc) : 0.0;
     }
+    if (!want_fit) return;
     __syncthreads();
-    if (want_fit && tid == 0) {
+    // ||Xhat||^2 = lam^T (Hadamard of all Grams) lam, in a fixed order
+    double xh = 0.0;
+    for (int e = tid; e < E; e += 256) {
+        const int r = e / R, c = e % R;
+        double h = 1.0;
+        for (int w = 0; w < nmodes; ++w) h *= grams[(int64_t)w * E + e];
+        xh += lam[r] * h * lam[c];
+    }
+    red[tid] = xh;
+    __syncthreads();
+    if (tid == 0) {
+        double x = 0.0;
+        for (int i = 0; i < 256; ++i) x += red[i];
         double in = 0.0;
-        for (int r = 0; r < R; ++r) in += inner[r];
-        double xh = 0.0;
-        for (int r = 0; r < R; ++r) {
-            for (int c = 0; c < R; ++c) {
-                double h = 1.0;
-                for (int w = 0; w < nmodes; ++w) h *= grams[(int64_t)w * E + r * R + c];
-                xh += lam[r] * h * lam[c];
-            }
-        }
-        double res2 = normX2 + xh - 2.0 * in;
+        for (int r = 0; r < R; ++r) in += Isum[r];
+        double res2 = normX2 + x - 2.0 * in;
         if (res2 < 0.0) res2 = 0.0;
         fit[0] = 1.0 - sqrt(res2) / sqrt(normX2);
     }
@@ -310,10 +324,9 @@ void launch_gram_partial(int rank, const float* Y, int64_t rows, double* partial
     by_rank<GramP>(rank, dim3(gram_blocks(rows)), dim3(256), s, Y, rows, partial);
 }
 
-void launch_gram_reduce(int rank, const double* partial, int nblocks, double* G, hipStream_t s) {
-    const int E = rank * rank;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((E + 255) / 256), dim3(256), 0, s, partial, nblocks,
-                       E, G);
+void launch_reduce_partials(const double* partial, int nblocks, int E, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((E + 31) / 32), dim3(256), 0, s, partial, nblocks,
+                       E, out);
 }
 
 void launch_normal_inverse(int rank, int nmodes, int mode, const double* grams, double* Vinv,
@@ -322,7 +335,7 @@ void launch_normal_inverse(int rank, int nmodes, int mode, const double* grams, 
 }
 
 int solve_blocks(int64_t rows) {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(2048, (rows + 63) / 64));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rows + 255) / 256));
 }
 
 void launch_solve_rows(int rank, const float* M, const double* Vinv, int64_t rows, float* Y,
@@ -330,11 +343,11 @@ void launch_solve_rows(int rank, const float* M, const double* Vinv, int64_t row
     by_rank<Solve>(rank, dim3(solve_blocks(rows)), dim3(256), s, M, Vinv, rows, Y, gpart, ipart);
 }
 
-void launch_als_finish(int rank, int nmodes, int mode, const double* gpart, const double* ipart,
-                       int nblocks, double* grams, double* lambda, double normX2, int want_fit,
-                       double* fit, hipStream_t s) {
-    by_rank<Finish>(rank, dim3(1), dim3(256), s, gpart, ipart, nblocks, nmodes, mode, grams, lambda,
-                    normX2, want_fit, fit);
+void launch_als_finish(int rank, int nmodes, int mode, const double* Gun, const double* Isum,
+                       double* grams, double* lambda, double normX2, int want_fit, double* fit,
+                       hipStream_t s) {
+    by_rank<Finish>(rank, dim3(1), dim3(256), s, Gun, Isum, nmodes, mode, grams, lambda, normX2,
+                    want_fit, fit);
 }
 
 void launch_scale_cols(int rank, float* Y, int64_t rows, const double* lambda, hipStream_t s) {

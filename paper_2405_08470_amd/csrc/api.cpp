@@ -79,12 +79,23 @@ struct spt_tensor_s {
     double* gpart = nullptr;
     double* ipart = nullptr;
     double* Vinv = nullptr;
+    double* Gsum = nullptr;
+    double* Isum = nullptr;
     double* fitd = nullptr;
     int32_t* status = nullptr;
     int32_t* status_host = nullptr;
     hipEvent_t status_event = nullptr;
     bool status_pending = false;
     std::vector<void*> ws_allocs;
+    // kernel timing
+    struct Timed {
+        int mode;
+        hipEvent_t ev[4];  // before EC, after EC, after fixup, after ALS step
+    };
+    bool timing = false;
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+    size_t events_used = 0;
 };
 
 namespace {
@@ -109,6 +120,8 @@ spt_status upload(spt_tensor_s* t, T** p, const std::vector<T>& v, hipStream_t s
 }
 
 void release(spt_tensor_s* t) {
+    for (hipEvent_t e : t->event_pool) (void)hipEventDestroy(e);
+    t->event_pool.clear();
     for (void* p : t->allocs) (void)hipFree(p);
     for (void* p : t->ws_allocs) (void)hipFree(p);
     if (t->status_host) (void)hipHostFree(t->status_host);
@@ -151,12 +164,27 @@ spt_status ensure_carry(spt_tensor_s* t, int rank) {
         if ((st = dalloc(t, &t->gpart, (size_t)(nb * E), &t->ws_allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->ipart, (size_t)(nb * rank), &t->ws_allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->Vinv, (size_t)E, &t->ws_allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->Gsum, (size_t)E, &t->ws_allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->Isum, (size_t)rank, &t->ws_allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->fitd, 1, &t->ws_allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->status, 1, &t->ws_allocs)) != SPT_OK) return st;
         HIPCHK(hipMemset(t->status, 0, sizeof(int32_t)));
     }
     t->ws_rank = rank;
     return SPT_OK;
+}
+
+// An event recorded on `s` now (timing only); nullptr if timing is off.
+hipEvent_t mark(spt_tensor_s* t, hipStream_t s) {
+    if (!t->timing) return nullptr;
+    if (t->events_used == t->event_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        t->event_pool.push_back(e);
+    }
+    hipEvent_t e = t->event_pool[t->events_used++];
+    if (hipEventRecord(e, s) != hipSuccess) return nullptr;
+    return e;
 }
 
 // mode d's stream buffer and, when remapping, the target buffer
@@ -188,9 +216,12 @@ spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int
         a.fshift[k] = t->lay.off[w] & 31;
         a.fmask[k] = (uint32_t)((uint64_t(1) << t->lay.bits[w]) - 1);
     }
+    spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr}};
+    tm.ev[0] = mark(t, s);
     if (!spt::launch_ec(N, rank, t->lay.words, t->kappa, a, s))
         return fail(SPT_ERR_UNSUPPORTED, "no kernel compiled for this mode count / rank / record size");
     HIPCHK(hipGetLastError());
+    tm.ev[1] = mark(t, s);
     spt::FixupArgs f{};
     f.out = out;
     f.carry = t->carry;
@@ -201,6 +232,8 @@ spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int
     f.nempty = t->nempty[mode];
     spt::launch_fixup(rank, f, s);
     HIPCHK(hipGetLastError());
+    tm.ev[2] = mark(t, s);
+    if (t->timing && tm.ev[0] && tm.ev[1] && tm.ev[2]) t->timed.push_back(tm);
     if (fuse && !t->copies) {
         t->cur = 1 - t->cur;
         t->cur_mode = (mode + 1) % N;
@@ -258,6 +291,10 @@ spt_status spt_plan_coo(int32_t nmodes, const int64_t* dims, int64_t nnz, const 
     if (!msg.empty()) return fail(range ? SPT_ERR_OUT_OF_RANGE : SPT_ERR_INVALID_ARG, msg);
     po.remap_ids = remap != nullptr;
     po.norm = false;
+    if (!part && !remap && !ptr) {
+        if (kappa_out) *kappa_out = po.kappa > 0 ? po.kappa : spt::default_kappa(nnz);
+        return SPT_OK;
+    }
     try {
         Plan plan;
         spt::build_plan(nmodes, dims, nnz, indices, nullptr, po, &plan);
@@ -311,8 +348,7 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
         const int W = t->lay.words;
         auto pack_stream = [&](const std::vector<int32_t>& order, std::vector<uint32_t>& recs) {
             recs.resize((size_t)nnz * W);
-            for (int64_t p = 0; p < nnz; ++p)
-                spt::pack_record(t->lay, indices, nnz, values, order[p], &recs[(size_t)p * W]);
+            spt::pack_stream(t->lay, indices, nnz, values, order.data(), recs.data());
         };
         std::vector<uint32_t> recs;
         std::vector<int32_t> nxt;
@@ -333,9 +369,9 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
                 pack_stream(mp.order, recs);
                 if ((st = upload(t, &t->rec_mode[d], recs, s)) != SPT_OK) break;
             } else {
-                const auto& nx = plan.mode[(d + 1) % nmodes].remap;
                 nxt.resize(nnz);
-                for (int64_t p = 0; p < nnz; ++p) nxt[p] = nx[mp.order[p]];
+                spt::next_positions(mp.order.data(), plan.mode[(d + 1) % nmodes].remap.data(), nnz,
+                                    nxt.data());
                 if ((st = upload(t, &t->nxt[d], nxt, s)) != SPT_OK) break;
             }
             // the uploads above read host vectors that are reused next mode
@@ -368,6 +404,32 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
     }
     t->prep_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = t;
+    return SPT_OK;
+}
+
+spt_status spt_timing_control(spt_tensor_t t, int32_t enable, spt_timing* out) {
+    g_last_error.clear();
+    if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
+    if (out) {
+        std::memset(out, 0, sizeof(*out));
+        for (const auto& tm : t->timed) {
+            HIPCHK(hipEventSynchronize(tm.ev[3] ? tm.ev[3] : tm.ev[2]));
+            float a = 0.f, b = 0.f, c = 0.f;
+            HIPCHK(hipEventElapsedTime(&a, tm.ev[0], tm.ev[1]));
+            HIPCHK(hipEventElapsedTime(&b, tm.ev[1], tm.ev[2]));
+            if (tm.ev[3]) HIPCHK(hipEventElapsedTime(&c, tm.ev[2], tm.ev[3]));
+            out->calls[tm.mode] += 1;
+            out->ec_ms[tm.mode] += a;
+            out->fixup_ms[tm.mode] += b;
+            out->als_ms[tm.mode] += c;
+        }
+    }
+    if (enable) {
+        HIPCHK(hipDeviceSynchronize());
+        t->timed.clear();
+        t->events_used = 0;
+    }
+    t->timing = enable != 0;
     return SPT_OK;
 }
 
@@ -461,7 +523,7 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
     for (int w = 1; w < N; ++w) {
         const int nb = spt::gram_blocks(t->dims[w]);
         spt::launch_gram_partial(rank, (const float*)factors[w], t->dims[w], t->gpart, s);
-        spt::launch_gram_reduce(rank, t->gpart, nb, t->grams + w * E, s);
+        spt::launch_reduce_partials(t->gpart, nb, (int)E, t->grams + w * E, s);
     }
     HIPCHK(hipGetLastError());
     for (int d = 0; d < N; ++d) {
@@ -471,10 +533,14 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
         const int nb = spt::solve_blocks(t->dims[d]);
         spt::launch_solve_rows(rank, t->M, t->Vinv, t->dims[d], (float*)factors[d], t->gpart,
                                t->ipart, s);
-        spt::launch_als_finish(rank, N, d, t->gpart, t->ipart, nb, t->grams, lambda, t->norm_sq,
+        spt::launch_reduce_partials(t->gpart, nb, (int)E, t->Gsum, s);
+        spt::launch_reduce_partials(t->ipart, nb, rank, t->Isum, s);
+        spt::launch_als_finish(rank, N, d, t->Gsum, t->Isum, t->grams, lambda, t->norm_sq,
                                (fit && d == N - 1) ? 1 : 0, t->fitd, s);
         spt::launch_scale_cols(rank, (float*)factors[d], t->dims[d], lambda, s);
         HIPCHK(hipGetLastError());
+        if (t->timing && !t->timed.empty() && t->timed.back().mode == d && !t->timed.back().ev[3])
+            t->timed.back().ev[3] = mark(t, s);
     }
     if (t->copies) t->cur_mode = 0;
     HIPCHK(hipMemcpyAsync(t->status_host, t->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));

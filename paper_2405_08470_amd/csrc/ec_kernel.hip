@@ -16,6 +16,8 @@
 // record is written to its remap position in the next mode's stream
 // (Alg. 3): consecutive records bound for the same (row, source partition)
 // in the next stream land in consecutive slots.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace spt {
@@ -244,19 +246,45 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     }
 }
 
-__global__ void fixup_kernel(const FixupArgs a, int R) {
-    const int64_t total = (int64_t)(a.nsplit + a.nempty) * R;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = i / R;
-        const int r = (int)(i % R);
-        if (j < a.nsplit) {
-            float s = 0.0f;
-            for (int k = a.split_ptr[j]; k < a.split_ptr[j + 1]; ++k) s += a.carry[(int64_t)k * R + r];
-            a.out[(int64_t)a.split_row[j] * R + r] = s;
-        } else {
-            a.out[(int64_t)a.empty_rows[j - a.nsplit] * R + r] = 0.0f;
+// Split rows: one workgroup per row sums its carry slots.  Thread (q, r)
+// adds slots q, q + Q, q + 2Q, ... of rank r in four interleaved chains,
+// then the Q partials are added in order of q -- a fixed order, so the
+// result does not depend on scheduling.  Blocks past the split rows fill
+// the rows that have no nonzero with zeros.
+template <int R>
+__global__ __launch_bounds__(1024) void fixup_kernel(const FixupArgs a, int zero_blocks) {
+    constexpr int Q = 1024 / R;
+    __shared__ float part[Q][R];
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x < a.nsplit) {
+        const int j = blockIdx.x;
+        const int q = tid / R, r = tid % R;
+        const int k0 = a.split_ptr[j], k1 = a.split_ptr[j + 1];
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        int k = k0 + q;
+        for (; k + 3 * Q < k1; k += 4 * Q) {
+            s0 += a.carry[(int64_t)k * R + r];
+            s1 += a.carry[(int64_t)(k + Q) * R + r];
+            s2 += a.carry[(int64_t)(k + 2 * Q) * R + r];
+            s3 += a.carry[(int64_t)(k + 3 * Q) * R + r];
         }
+        for (; k < k1; k += Q) s0 += a.carry[(int64_t)k * R + r];
+        part[q][r] = (s0 + s1) + (s2 + s3);
+        __syncthreads();
+        if (tid < R) {
+            float t = 0.f;
+            for (int i = 0; i < Q; ++i) t += part[i][tid];
+            a.out[(int64_t)a.split_row[j] * R + tid] = t;
+        }
+        return;
+    }
+    // zero rows: float4 per thread
+    constexpr int R4 = R / 4;
+    const int64_t total = (int64_t)a.nempty * R4;
+    const int64_t stride = (int64_t)zero_blocks * 1024;
+    for (int64_t i = (int64_t)(blockIdx.x - a.nsplit) * 1024 + tid; i < total; i += stride) {
+        const int64_t row = a.empty_rows[i / R4];
+        reinterpret_cast<float4*>(a.out + row * R)[i % R4] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
@@ -317,11 +345,18 @@ bool launch_ec(int nmodes, int rank, int words, int kappa, const EcArgs& a, hipS
 }
 
 void launch_fixup(int rank, const FixupArgs& a, hipStream_t s) {
-    const int64_t total = (int64_t)(a.nsplit + a.nempty) * rank;
-    if (total == 0) return;
-    const int threads = 256;
-    const int64_t blocks = std::min<int64_t>((total + threads - 1) / threads, 4096);
-    hipLaunchKernelGGL(fixup_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, a, rank);
+    const int64_t zero_work = (int64_t)a.nempty * (rank / 4);
+    const int zero_blocks = (int)std::min<int64_t>((zero_work + 1023) / 1024, 1024);
+    const int blocks = a.nsplit + zero_blocks;
+    if (blocks == 0) return;
+    switch (rank) {
+        case 8: hipLaunchKernelGGL(fixup_kernel<8>, dim3(blocks), dim3(1024), 0, s, a, zero_blocks); break;
+        case 16: hipLaunchKernelGGL(fixup_kernel<16>, dim3(blocks), dim3(1024), 0, s, a, zero_blocks); break;
+        case 32: hipLaunchKernelGGL(fixup_kernel<32>, dim3(blocks), dim3(1024), 0, s, a, zero_blocks); break;
+        case 64: hipLaunchKernelGGL(fixup_kernel<64>, dim3(blocks), dim3(1024), 0, s, a, zero_blocks); break;
+        case 128: hipLaunchKernelGGL(fixup_kernel<128>, dim3(blocks), dim3(1024), 0, s, a, zero_blocks); break;
+        default: break;
+    }
 }
 
 void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,

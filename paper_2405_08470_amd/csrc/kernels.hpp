@@ -48,8 +48,8 @@ void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,
 int gram_blocks(int64_t rows);
 // partial[b][R*R] for b < gram_blocks(rows)
 void launch_gram_partial(int rank, const float* Y, int64_t rows, double* partial, hipStream_t s);
-// G = sum of partials; G is R x R
-void launch_gram_reduce(int rank, const double* partial, int nblocks, double* G, hipStream_t s);
+// out[e] = sum_b partial[b][e] (fixed order), e < E
+void launch_reduce_partials(const double* partial, int nblocks, int E, double* out, hipStream_t s);
 // V = Hadamard of grams[w] (w != mode); Cholesky; Vinv.  status[0] |= 1 on
 // failure after one ridge retry.
 void launch_normal_inverse(int rank, int nmodes, int mode, const double* grams, double* Vinv,
@@ -58,11 +58,12 @@ void launch_normal_inverse(int rank, int nmodes, int mode, const double* grams, 
 int solve_blocks(int64_t rows);
 void launch_solve_rows(int rank, const float* M, const double* Vinv, int64_t rows, float* Y,
                        double* gpart, double* ipart, hipStream_t s);
-// From the partials: G_un, lambda = sqrt(diag), G_mode = D^-1 G_un D^-1,
-// inner_r; if want_fit, fit[0] from all grams, lambda and normX2.
-void launch_als_finish(int rank, int nmodes, int mode, const double* gpart, const double* ipart,
-                       int nblocks, double* grams, double* lambda, double normX2, int want_fit,
-                       double* fit, hipStream_t s);
+// From the reduced sums G_un (R x R) and Isum (R): lambda = sqrt(diag G_un),
+// grams[mode] = D^-1 G_un D^-1; if want_fit, fit[0] from all grams, lambda,
+// Isum and normX2.
+void launch_als_finish(int rank, int nmodes, int mode, const double* Gun, const double* Isum,
+                       double* grams, double* lambda, double normX2, int want_fit, double* fit,
+                       hipStream_t s);
 void launch_scale_cols(int rank, float* Y, int64_t rows, const double* lambda, hipStream_t s);
 // p[0..n) = 0 with a kernel (no memset node when a caller captures a graph)
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);

@@ -76,4 +76,10 @@ void pack_record(const RecordLayout& lay, const int32_t* idx, int64_t nnz, const
                  int64_t e, uint32_t* out);
 void unpack_record(const RecordLayout& lay, const uint32_t* rec, int32_t* c, float* v);
 
+// out[p] = packed record of nonzero order[p], p < nnz (multithreaded).
+void pack_stream(const RecordLayout& lay, const int32_t* idx, int64_t nnz, const float* val,
+                 const int32_t* order, uint32_t* out);
+// nxt[p] = remap_next[order[p]] (multithreaded).
+void next_positions(const int32_t* order, const int32_t* remap_next, int64_t nnz, int32_t* nxt);
+
 }  // namespace spt

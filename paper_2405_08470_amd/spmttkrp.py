@@ -47,9 +47,15 @@ class spt_info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64)]
 
 
+class spt_timing(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64 * 8), ("ec_ms", ctypes.c_double * 8),
+                ("fixup_ms", ctypes.c_double * 8), ("als_ms", ctypes.c_double * 8)]
+
+
 EXPORTS = ["spt_tensor_load_coo", "spt_remap_for_mode", "spt_mttkrp", "spt_cp_als_iter",
-           "spt_tensor_info", "spt_tensor_get_remap", "spt_tensor_get_records", "spt_tensor_free",
-           "spt_plan_coo", "spt_status_str", "spt_last_error"]
+           "spt_tensor_info", "spt_tensor_get_remap", "spt_tensor_get_records",
+           "spt_timing_control", "spt_tensor_free", "spt_plan_coo", "spt_status_str",
+           "spt_last_error"]
 
 _lib = None
 
@@ -70,6 +76,7 @@ def lib() -> ctypes.CDLL:
     L.spt_tensor_get_remap.argtypes = [vp, i32, vp]
     L.spt_tensor_get_records.argtypes = [vp, vp, vp, vp]
     L.spt_tensor_free.argtypes = [vp]
+    L.spt_timing_control.argtypes = [vp, i32, vp]
     L.spt_plan_coo.argtypes = [i32, vp, i64, vp, vp, vp, vp, vp, vp]
     L.spt_status_str.argtypes = [i32]
     L.spt_status_str.restype = ctypes.c_char_p
@@ -241,6 +248,19 @@ def tensor_get_records(t: Tensor):
     _check(lib().spt_tensor_get_records(t.handle, idx.ctypes.data, val.ctypes.data,
                                         ctypes.byref(cur)))
     return idx, val, cur.value
+
+
+def timing_control(t: Tensor, enable: bool, want: bool = True) -> Optional[Dict[str, list]]:
+    """Returns the per-mode kernel-time totals so far (if want), then starts
+    (enable) or stops recording."""
+    tm = spt_timing()
+    _check(lib().spt_timing_control(t.handle, 1 if enable else 0,
+                                    ctypes.byref(tm) if want else None))
+    if not want:
+        return None
+    N = t.nmodes
+    return {"calls": list(tm.calls[:N]), "ec_ms": list(tm.ec_ms[:N]),
+            "fixup_ms": list(tm.fixup_ms[:N]), "als_ms": list(tm.als_ms[:N])}
 
 
 def tensor_free(t: Tensor) -> None:
