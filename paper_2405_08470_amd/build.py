@@ -39,26 +39,28 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, out: str = LIB, defines=(), objdir: str = OBJ) -> str:
+    """Compiles every source and links `out`; `defines` are extra -D flags."""
+    os.makedirs(objdir, exist_ok=True)
+    dflags = [f"-D{d}" for d in defines]
     jobs = []
     for s in HOST_SOURCES:
-        o = os.path.join(OBJ, s + ".o")
-        jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, s), "-o", o])
+        o = os.path.join(objdir, s + ".o")
+        jobs.append(["g++", *HOST_FLAGS, *dflags, "-c", os.path.join(CSRC, s), "-o", o])
     for s in HIP_SOURCES:
-        o = os.path.join(OBJ, s + ".o")
-        jobs.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, s), "-o", o])
+        o = os.path.join(objdir, s + ".o")
+        jobs.append([HIPCC, *HIP_FLAGS, *dflags, "-c", os.path.join(CSRC, s), "-o", o])
     with ThreadPoolExecutor(max(1, min(8, len(jobs)))) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:
         for o in outs:
             if o.strip():
                 print(o)
-    objs = [os.path.join(OBJ, s + ".o") for s in HOST_SOURCES + HIP_SOURCES]
-    tmp = LIB + ".tmp"
+    objs = [os.path.join(objdir, s + ".o") for s in HOST_SOURCES + HIP_SOURCES]
+    tmp = out + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -212,13 +212,13 @@ spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int
     for (int k = 0; k < N; ++k) {
         const int w = (mode + k) % N;
         a.fac[k] = (const float*)factors[w];
-        a.fword[k] = t->lay.off[w] >> 5;
-        a.fshift[k] = t->lay.off[w] & 31;
-        a.fmask[k] = (uint32_t)((uint64_t(1) << t->lay.bits[w]) - 1);
+        a.rot[k] = w;
+        a.foff[k] = t->lay.off[k];
+        a.fmask[k] = (uint32_t)((uint64_t(1) << t->lay.bits[k]) - 1);
     }
     spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr}};
     tm.ev[0] = mark(t, s);
-    if (!spt::launch_ec(N, rank, t->lay.words, t->kappa, a, s))
+    if (!spt::launch_ec(N, rank, t->lay.words, t->lay.kind, t->kappa, a, s))
         return fail(SPT_ERR_UNSUPPORTED, "no kernel compiled for this mode count / rank / record size");
     HIPCHK(hipGetLastError());
     tm.ev[1] = mark(t, s);

@@ -12,56 +12,71 @@
 // at the end.  Rows split across partitions (pieces, see the planner) go to
 // a carry slot instead, summed later by the fixup kernel.  No atomics.
 //
-// Records are fetched 64 at a time, one per lane, which is also where each
-// record is written to its remap position in the next mode's stream
-// (Alg. 3): consecutive records bound for the same (row, source partition)
-// in the next stream land in consecutive slots.
+// Records are fetched one step ahead, one per lane (software pipeline),
+// which is also where each record is written to its remap position in the
+// next mode's stream (Alg. 3).  Each lane decodes the record it fetched into
+// LDS once; the gathers of several nonzeros are issued before any of them is
+// consumed.
 #include <algorithm>
+#include <utility>
 
 #include "kernels.hpp"
+
+// float4 gathers a lane keeps in flight (register budget of the batch)
+#ifndef SPT_GATHER_INFLIGHT
+#define SPT_GATHER_INFLIGHT 16
+#endif
 
 namespace spt {
 
 namespace {
 
-template <int W>
-__device__ __forceinline__ uint32_t pick_word(const uint32_t (&r)[W], int k) {
-    uint32_t v = r[0];
-#pragma unroll
-    for (int i = 1; i < W; ++i) v = (k == i) ? r[i] : v;
-    return v;
+template <int RW>
+struct Rec {
+    uint4 q[RW / 4];
+};
+
+template <int W, int RW>
+__device__ __forceinline__ uint32_t rword(const Rec<RW>& r) {
+    static_assert(W < RW, "word");
+    const uint4& v = r.q[W / 4];
+    return (W % 4 == 0) ? v.x : (W % 4 == 1) ? v.y : (W % 4 == 2) ? v.z : v.w;
 }
 
 template <int RW>
-__device__ __forceinline__ uint32_t field(const uint32_t (&r)[RW], int wi, int sh, uint32_t mask) {
-    // indices occupy words 0 .. RW-2; word RW-1 is the value
-    uint32_t lo = pick_word<RW - 1>(reinterpret_cast<const uint32_t(&)[RW - 1]>(r), wi);
-    uint32_t hi = pick_word<RW - 1>(reinterpret_cast<const uint32_t(&)[RW - 1]>(r), wi + 1);
-    hi = (wi + 1 < RW - 1) ? hi : 0u;
-    return __builtin_amdgcn_alignbit(hi, lo, (uint32_t)sh) & mask;
+__device__ __forceinline__ void load_rec(const uint32_t* __restrict__ base, int64_t p, Rec<RW>& r) {
+    const uint4* src = reinterpret_cast<const uint4*>(base + p * RW);
+#pragma unroll
+    for (int k = 0; k < RW / 4; ++k) r.q[k] = src[k];
 }
 
 template <int RW>
-__device__ __forceinline__ void load_record(const uint32_t* __restrict__ base, int64_t p,
-                                            uint32_t (&r)[RW]) {
-    const uint4* q = reinterpret_cast<const uint4*>(base + p * RW);
+__device__ __forceinline__ void store_rec(uint32_t* __restrict__ base, int64_t p, const Rec<RW>& r) {
+    uint4* dst = reinterpret_cast<uint4*>(base + p * RW);
 #pragma unroll
-    for (int k = 0; k < RW / 4; ++k) {
-        uint4 v = q[k];
-        r[4 * k + 0] = v.x;
-        r[4 * k + 1] = v.y;
-        r[4 * k + 2] = v.z;
-        r[4 * k + 3] = v.w;
+    for (int k = 0; k < RW / 4; ++k) dst[k] = r.q[k];
+}
+
+// Index of mode W in a record (layout kinds of the planner).
+template <int W, int RW, int KIND>
+__device__ __forceinline__ uint32_t decode(const Rec<RW>& r, const EcArgs& a) {
+    if constexpr (KIND == kWord32) {
+        return rword<W, RW>(r);
+    } else if constexpr (KIND == kHalf16) {
+        return (rword<W / 2, RW>(r) >> ((W & 1) * 16)) & 0xFFFFu;
+    } else {  // packed into the first 96 bits of a 16-byte record
+        const uint64_t lo = ((uint64_t)rword<1, RW>(r) << 32) | rword<0, RW>(r);
+        const uint64_t hi = rword<2, RW>(r);
+        const int o = a.foff[W];
+        const uint64_t x = o >= 64 ? (hi >> (o - 64)) : ((lo >> o) | (o ? (hi << (64 - o)) : 0));
+        return (uint32_t)x & a.fmask[W];
     }
 }
 
-template <int RW>
-__device__ __forceinline__ void store_record(uint32_t* __restrict__ base, int64_t p,
-                                             const uint32_t (&r)[RW]) {
-    uint4* q = reinterpret_cast<uint4*>(base + p * RW);
-#pragma unroll
-    for (int k = 0; k < RW / 4; ++k)
-        q[k] = make_uint4(r[4 * k + 0], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
+template <int RW, int KIND, int... W>
+__device__ __forceinline__ void decode_all(const Rec<RW>& r, const EcArgs& a, uint32_t (*st)[64],
+                                           int lane, std::integer_sequence<int, W...>) {
+    ((st[W][lane] = decode<W, RW, KIND>(r, a)), ...);
 }
 
 // Carry slot of `row` if it is a split row of this partition, else -1.
@@ -72,18 +87,33 @@ __device__ __forceinline__ int split_slot(const EcArgs& a, int sp0, int sp1, int
     return slot;
 }
 
-template <int N, int R, int RW>
+template <int R>
+__device__ __forceinline__ float* row_dst(const EcArgs& a, int row, int slot) {
+    return slot >= 0 ? a.carry + (int64_t)slot * R : a.out + (int64_t)row * R;
+}
+
+template <int N, int R, int RW, int KIND>
 __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     constexpr int V = 4;
     constexpr int L = R / V;     // lanes per nonzero
     constexpr int G = 64 / L;    // lane groups = nonzeros in flight
-    constexpr int SW = N + 1;    // staged words: rotated indices, value
-    static_assert(R % V == 0 && 64 % L == 0, "rank");
+    constexpr int NG = N - 1;    // gathered factor rows per nonzero
+    // nonzeros whose gathers are issued together: the largest divisor of L
+    // with at most SPT_GATHER_INFLIGHT float4 gathers in flight per lane
+    constexpr int BMAX = (SPT_GATHER_INFLIGHT / NG) > 0 ? SPT_GATHER_INFLIGHT / NG : 1;
+    constexpr int B = L <= BMAX ? L : (L / 2 <= BMAX ? L / 2 : (L / 4 <= BMAX ? L / 4 : (L / 8 <= BMAX ? L / 8 : 1)));
+    static_assert(R % V == 0 && 64 % L == 0 && L % B == 0, "rank");
+    // staged words per nonzero: indices in mode order, value, carry slot
+    constexpr int SW = N + 2;
+    constexpr int MAXSPLIT = 64;  // split rows of a partition kept in LDS
 
     __shared__ uint32_t stage[SW][64];
     __shared__ float part[2][G][R];   // [0] head, [1] tail partial of a group
     __shared__ int32_t prow[2][G];
+    __shared__ int32_t pslot[2][G];
     __shared__ int32_t gflag[G];      // bit 0 open-left, bit 1 open-right, bit 2 non-empty
+    __shared__ uint32_t brow[G][4];   // rows at the sub-range boundaries
+    __shared__ int32_t srow[MAXSPLIT], sslot[MAXSPLIT];
 
     const int z = blockIdx.x;
     const int lane = threadIdx.x;
@@ -93,101 +123,149 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     const int64_t n = a.ptr[z + 1] - s;
     if (n == 0) return;
     const int sp0 = a.psplit_ptr[z], sp1 = a.psplit_ptr[z + 1];
+    const int nsp = sp1 - sp0;
+    const bool sp_lds = nsp <= MAXSPLIT;
+    if (sp_lds && lane < nsp) {
+        srow[lane] = a.psplit_row[sp0 + lane];
+        sslot[lane] = a.psplit_slot[sp0 + lane];
+    }
+    const int mode = a.rot[0];
+    constexpr auto seq = std::make_integer_sequence<int, N>{};
 
     const int64_t q = n / G, rm = n % G;
     const int64_t gs = s + g * q + (g < rm ? g : rm);
-    const int64_t gn = q + (g < rm ? 1 : 0);
+    const int gn = (int)(q + (g < rm ? 1 : 0));
     const int64_t ge = gs + gn;
 
-    // Does the group's first / last row continue from / into a neighbour?
-    bool open_left = false, open_right = false;
-    if (gn > 0) {
-        uint32_t r0[RW], r1[RW];
-        load_record<RW>(a.rec_in, gs, r0);
-        load_record<RW>(a.rec_in, ge - 1, r1);
-        const uint32_t first_row = field<RW>(r0, a.fword[0], a.fshift[0], a.fmask[0]);
-        const uint32_t last_row = field<RW>(r1, a.fword[0], a.fshift[0], a.fmask[0]);
-        if (gs > s) {
-            uint32_t rp[RW];
-            load_record<RW>(a.rec_in, gs - 1, rp);
-            open_left = field<RW>(rp, a.fword[0], a.fshift[0], a.fmask[0]) == first_row;
+    // output rows around the group's sub-range: before, first, last, after
+    for (int j = li; j < 4; j += L) {
+        const int64_t p = j == 0 ? gs - 1 : j == 1 ? gs : j == 2 ? ge - 1 : ge;
+        uint32_t row = 0xFFFFFFFFu;
+        if (gn > 0 && p >= s && p < s + n) {
+            Rec<RW> r;
+            load_rec<RW>(a.rec_in, p, r);
+            decode_all<RW, KIND>(r, a, stage, lane, seq);
+            row = stage[mode][lane];
         }
-        if (ge < s + n) {
-            uint32_t rn[RW];
-            load_record<RW>(a.rec_in, ge, rn);
-            open_right = field<RW>(rn, a.fword[0], a.fshift[0], a.fmask[0]) == last_row;
-        }
+        brow[g][j] = row;
     }
+    __syncthreads();
+    const bool open_left = gn > 0 && brow[g][0] != 0xFFFFFFFFu && brow[g][0] == brow[g][1];
+    const bool open_right = gn > 0 && brow[g][3] != 0xFFFFFFFFu && brow[g][3] == brow[g][2];
     if (li == 0) {
         gflag[g] = (open_left ? 1 : 0) | (open_right ? 2 : 0) | (gn > 0 ? 4 : 0);
         prow[0][g] = -1;
         prow[1][g] = -1;
     }
+    __syncthreads();
 
     float acc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = 0.0f;
-    int cur_row = -1;
+    int cur_row = -1, cur_slot = -1;
     bool first_seg = true;
-    const int64_t steps = q + (rm > 0 ? 1 : 0);
+    const int steps = (int)(q + (rm > 0 ? 1 : 0));
+    const bool remap = a.rec_out != nullptr;
 
-    for (int64_t t = 0; t < steps; t += L) {
-        // stage: lane li of group g fetches nonzero gs + t + li
+    // carry slot of a row of this partition (-1: not a split row)
+    auto slot_of = [&](int row) {
+        int slot = -1;
+        if (sp_lds) {
+            for (int j = 0; j < nsp; ++j)
+                if (srow[j] == row) slot = sslot[j];
+        } else {
+            slot = split_slot(a, sp0, sp1, row);
+        }
+        return slot;
+    };
+
+    // One step: commit the record fetched for this step (remap store,
+    // decode), prefetch the next step's record into the other buffer, then
+    // run the lane groups over their L nonzeros of this step.
+    auto step = [&](int t, Rec<RW>& cur, int32_t& ncur, Rec<RW>& nxt_rec, int32_t& nnext) {
         if (t + li < gn) {
-            const int64_t p = gs + t + li;
-            uint32_t r[RW];
-            load_record<RW>(a.rec_in, p, r);
-            if (a.rec_out) store_record<RW>(a.rec_out, a.nxt[p], r);
-#pragma unroll
-            for (int k = 0; k < N; ++k)
-                stage[k][lane] = field<RW>(r, a.fword[k], a.fshift[k], a.fmask[k]);
-            stage[N][lane] = r[RW - 1];
+            if (remap) store_rec<RW>(a.rec_out, ncur, cur);
+            decode_all<RW, KIND>(cur, a, stage, lane, seq);
+            stage[N][lane] = rword<RW - 1, RW>(cur);
+            stage[N + 1][lane] = (uint32_t)slot_of((int)stage[mode][lane]);
         }
         __syncthreads();
-        const int64_t cnt = gn - t;
+        const int cnt = gn - t;
 #pragma unroll
-        for (int kk = 0; kk < L; ++kk) {
-            if (kk < cnt) {
-                const int slot = g * L + kk;
-                const int row = (int)stage[0][slot];
-                if (row != cur_row) {
-                    if (cur_row >= 0) {
-                        if (first_seg && open_left) {
+        for (int kb = 0; kb < L; kb += B) {
+            float4 y[B][NG];
+            // issue every gather of the batch first
 #pragma unroll
-                            for (int v = 0; v < V; ++v) part[0][g][li * V + v] = acc[v];
-                            if (li == 0) prow[0][g] = cur_row;
-                        } else {
-                            const int sl = split_slot(a, sp0, sp1, cur_row);
-                            float* dst = sl >= 0 ? a.carry + (int64_t)sl * R
-                                                 : a.out + (int64_t)cur_row * R;
-                            *reinterpret_cast<float4*>(dst + li * V) =
-                                make_float4(acc[0], acc[1], acc[2], acc[3]);
+            for (int b = 0; b < B; ++b) {
+                if (kb + b < cnt) {
+                    const int slot = g * L + kb + b;
+#pragma unroll
+                    for (int k = 0; k < NG; ++k)
+                        y[b][k] = *reinterpret_cast<const float4*>(
+                            a.fac[k + 1] + (int64_t)stage[a.rot[k + 1]][slot] * R + li * V);
+                }
+            }
+            if (kb == 0 && t + L + li < gn) {
+                // after the first gathers, so waiting for those does not wait
+                // for this (memory counters retire in issue order)
+                load_rec<RW>(a.rec_in, gs + t + L + li, nxt_rec);
+                if (remap) nnext = a.nxt[gs + t + L + li];
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (kb + b < cnt) {
+                    const int slot = g * L + kb + b;
+                    const int row = (int)stage[mode][slot];
+                    if (row != cur_row) {
+                        if (cur_row >= 0) {
+                            if (first_seg && open_left) {
+#pragma unroll
+                                for (int v = 0; v < V; ++v) part[0][g][li * V + v] = acc[v];
+                                if (li == 0) {
+                                    prow[0][g] = cur_row;
+                                    pslot[0][g] = cur_slot;
+                                }
+                            } else {
+                                *reinterpret_cast<float4*>(row_dst<R>(a, cur_row, cur_slot) + li * V) =
+                                    make_float4(acc[0], acc[1], acc[2], acc[3]);
+                            }
+                            first_seg = false;
                         }
-                        first_seg = false;
+                        cur_row = row;
+                        cur_slot = (int)stage[N + 1][slot];
+#pragma unroll
+                        for (int v = 0; v < V; ++v) acc[v] = 0.0f;
                     }
-                    cur_row = row;
+                    const float val = __uint_as_float(stage[N][slot]);
+                    float4 prod = y[b][0];
 #pragma unroll
-                    for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+                    for (int k = 1; k < NG; ++k) {
+                        prod.x *= y[b][k].x;
+                        prod.y *= y[b][k].y;
+                        prod.z *= y[b][k].z;
+                        prod.w *= y[b][k].w;
+                    }
+                    acc[0] = fmaf(prod.x, val, acc[0]);
+                    acc[1] = fmaf(prod.y, val, acc[1]);
+                    acc[2] = fmaf(prod.z, val, acc[2]);
+                    acc[3] = fmaf(prod.w, val, acc[3]);
                 }
-                const float val = __uint_as_float(stage[N][slot]);
-                float4 prod = *reinterpret_cast<const float4*>(
-                    a.fac[1] + (int64_t)stage[1][slot] * R + li * V);
-#pragma unroll
-                for (int k = 2; k < N; ++k) {
-                    const float4 y = *reinterpret_cast<const float4*>(
-                        a.fac[k] + (int64_t)stage[k][slot] * R + li * V);
-                    prod.x *= y.x;
-                    prod.y *= y.y;
-                    prod.z *= y.z;
-                    prod.w *= y.w;
-                }
-                acc[0] = fmaf(prod.x, val, acc[0]);
-                acc[1] = fmaf(prod.y, val, acc[1]);
-                acc[2] = fmaf(prod.z, val, acc[2]);
-                acc[3] = fmaf(prod.w, val, acc[3]);
             }
         }
         __syncthreads();
+    };
+
+    // two record buffers, alternating, so a prefetch never overwrites the
+    // registers of a remap store still in flight
+    Rec<RW> ra, rb;
+    int32_t na = 0, nb = 0;
+    if (li < gn) {
+        load_rec<RW>(a.rec_in, gs + li, ra);
+        if (remap) na = a.nxt[gs + li];
+    }
+    for (int t = 0; t < steps; t += 2 * L) {
+        step(t, ra, na, rb, nb);
+        if (t + L < steps) step(t + L, rb, nb, ra, na);
     }
 
     // the group's last segment
@@ -195,11 +273,13 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
         if (open_right || (first_seg && open_left)) {
 #pragma unroll
             for (int v = 0; v < V; ++v) part[1][g][li * V + v] = acc[v];
-            if (li == 0) prow[1][g] = cur_row;
+            if (li == 0) {
+                prow[1][g] = cur_row;
+                pslot[1][g] = cur_slot;
+            }
         } else {
-            const int sl = split_slot(a, sp0, sp1, cur_row);
-            float* dst = sl >= 0 ? a.carry + (int64_t)sl * R : a.out + (int64_t)cur_row * R;
-            *reinterpret_cast<float4*>(dst + li * V) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            *reinterpret_cast<float4*>(row_dst<R>(a, cur_row, cur_slot) + li * V) =
+                make_float4(acc[0], acc[1], acc[2], acc[3]);
         }
     }
     __syncthreads();
@@ -209,37 +289,37 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
         const int rk = r0 + lane;
         const bool active = rk < R;
         float csum = 0.0f;
-        int crow = -1;
+        int crow = -1, cslot = -1;
         for (int h = 0; h < G; ++h) {
             const int f = gflag[h];
             if (!(f & 4)) continue;
             const bool ol = f & 1, orr = f & 2;
-            auto flush = [&](int row, float x) {
+            auto flush = [&](int row, int slot, float x) {
                 if (row < 0) return;
-                const int sl = split_slot(a, sp0, sp1, row);
-                float* dst = sl >= 0 ? a.carry + (int64_t)sl * R : a.out + (int64_t)row * R;
-                if (active) dst[rk] = x;
+                if (active) row_dst<R>(a, row, slot)[rk] = x;
             };
             if (ol) {
                 if (prow[0][h] >= 0) {
                     csum += active ? part[0][h][rk] : 0.0f;
-                    flush(crow, csum);
+                    flush(crow, cslot, csum);
                     crow = -1;
                     csum = 0.0f;
                     if (prow[1][h] >= 0) {
                         crow = prow[1][h];
+                        cslot = pslot[1][h];
                         csum = active ? part[1][h][rk] : 0.0f;
                     }
                 } else {
                     csum += active ? part[1][h][rk] : 0.0f;
                     if (!orr) {
-                        flush(crow, csum);
+                        flush(crow, cslot, csum);
                         crow = -1;
                         csum = 0.0f;
                     }
                 }
             } else if (prow[1][h] >= 0) {
                 crow = prow[1][h];
+                cslot = pslot[1][h];
                 csum = active ? part[1][h][rk] : 0.0f;
             }
         }
@@ -299,47 +379,55 @@ __global__ void remap_kernel(const uint32_t* __restrict__ in, uint32_t* __restri
          p += (int64_t)gridDim.x * blockDim.x) {
         int64_t d = p;
         for (int h = 0; h < hops; ++h) d = ch.nxt[h][d];
-        uint32_t r[RW];
-        load_record<RW>(in, p, r);
-        store_record<RW>(out, d, r);
+        Rec<RW> r;
+        load_rec<RW>(in, p, r);
+        store_rec<RW>(out, d, r);
     }
 }
 
-template <int N, int R, int RW>
-void launch_one(int kappa, const EcArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((ec_kernel<N, R, RW>), dim3(kappa), dim3(64), 0, s, a);
-}
-
-template <int N, int RW>
+template <int N, int RW, int KIND>
 bool by_rank(int rank, int kappa, const EcArgs& a, hipStream_t s) {
+    const dim3 grid(kappa), block(64);
     switch (rank) {
-        case 8: launch_one<N, 8, RW>(kappa, a, s); return true;
-        case 16: launch_one<N, 16, RW>(kappa, a, s); return true;
-        case 32: launch_one<N, 32, RW>(kappa, a, s); return true;
-        case 64: launch_one<N, 64, RW>(kappa, a, s); return true;
-        case 128: launch_one<N, 128, RW>(kappa, a, s); return true;
+        case 8: hipLaunchKernelGGL((ec_kernel<N, 8, RW, KIND>), grid, block, 0, s, a); return true;
+        case 16: hipLaunchKernelGGL((ec_kernel<N, 16, RW, KIND>), grid, block, 0, s, a); return true;
+        case 32: hipLaunchKernelGGL((ec_kernel<N, 32, RW, KIND>), grid, block, 0, s, a); return true;
+        case 64: hipLaunchKernelGGL((ec_kernel<N, 64, RW, KIND>), grid, block, 0, s, a); return true;
+        case 128: hipLaunchKernelGGL((ec_kernel<N, 128, RW, KIND>), grid, block, 0, s, a); return true;
         default: return false;
     }
 }
 
+// (record words, layout kind) pairs the planner can choose for N modes
 template <int N>
-bool by_words(int rank, int words, int kappa, const EcArgs& a, hipStream_t s) {
-    if (words == 4) return by_rank<N, 4>(rank, kappa, a, s);
-    if (words == 8) return by_rank<N, 8>(rank, kappa, a, s);
+bool by_layout(int rank, int words, int kind, int kappa, const EcArgs& a, hipStream_t s) {
+    if constexpr (N <= 3) {
+        if (words == 4 && kind == kWord32) return by_rank<N, 4, kWord32>(rank, kappa, a, s);
+    } else if constexpr (N <= 6) {
+        if (words == 4 && kind == kHalf16) return by_rank<N, 4, kHalf16>(rank, kappa, a, s);
+        if (words == 4 && kind == kPacked) return by_rank<N, 4, kPacked>(rank, kappa, a, s);
+        if (words == 8 && kind == kWord32) return by_rank<N, 8, kWord32>(rank, kappa, a, s);
+    } else if constexpr (N == 7) {
+        if (words == 8 && kind == kWord32) return by_rank<N, 8, kWord32>(rank, kappa, a, s);
+    } else {
+        if (words == 8 && kind == kHalf16) return by_rank<N, 8, kHalf16>(rank, kappa, a, s);
+        if (words == 12 && kind == kWord32) return by_rank<N, 12, kWord32>(rank, kappa, a, s);
+    }
     return false;
 }
 
 }  // namespace
 
-bool launch_ec(int nmodes, int rank, int words, int kappa, const EcArgs& a, hipStream_t s) {
+bool launch_ec(int nmodes, int rank, int words, int kind, int kappa, const EcArgs& a,
+               hipStream_t s) {
     switch (nmodes) {
-        case 2: return by_words<2>(rank, words, kappa, a, s);
-        case 3: return by_words<3>(rank, words, kappa, a, s);
-        case 4: return by_words<4>(rank, words, kappa, a, s);
-        case 5: return by_words<5>(rank, words, kappa, a, s);
-        case 6: return by_words<6>(rank, words, kappa, a, s);
-        case 7: return by_words<7>(rank, words, kappa, a, s);
-        case 8: return by_words<8>(rank, words, kappa, a, s);
+        case 2: return by_layout<2>(rank, words, kind, kappa, a, s);
+        case 3: return by_layout<3>(rank, words, kind, kappa, a, s);
+        case 4: return by_layout<4>(rank, words, kind, kappa, a, s);
+        case 5: return by_layout<5>(rank, words, kind, kappa, a, s);
+        case 6: return by_layout<6>(rank, words, kind, kappa, a, s);
+        case 7: return by_layout<7>(rank, words, kind, kappa, a, s);
+        case 8: return by_layout<8>(rank, words, kind, kappa, a, s);
         default: return false;
     }
 }
@@ -369,8 +457,11 @@ void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,
     if (words == 4)
         hipLaunchKernelGGL((remap_kernel<4>), dim3((unsigned)blocks), dim3(threads), 0, s, in, out,
                            nnz, ch, hops);
-    else
+    else if (words == 8)
         hipLaunchKernelGGL((remap_kernel<8>), dim3((unsigned)blocks), dim3(threads), 0, s, in, out,
+                           nnz, ch, hops);
+    else
+        hipLaunchKernelGGL((remap_kernel<12>), dim3((unsigned)blocks), dim3(threads), 0, s, in, out,
                            nnz, ch, hops);
 }
 

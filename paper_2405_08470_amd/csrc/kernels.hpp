@@ -5,13 +5,15 @@
 
 #include <cstdint>
 
+#include "plan.hpp"
+
 namespace spt {
 
 // Arguments of the fused elementwise-computation / remapping kernel for one
 // output mode d.  Everything "rotated" is indexed k = 0..N-1 for mode
 // (d + k) mod N, so k = 0 is the output mode.
 struct EcArgs {
-    const uint32_t* rec_in;    // packed records of mode d's stream
+    const uint32_t* rec_in;    // records of mode d's stream
     uint32_t* rec_out;         // remap target in mode d+1's order, or nullptr
     const int32_t* nxt;        // [nnz] position in mode d+1 of the record at p
     const int64_t* ptr;        // [kappa+1] partition offsets of mode d
@@ -20,10 +22,10 @@ struct EcArgs {
     const int32_t* psplit_slot;
     float* out;                // I_d x R
     float* carry;              // nslots x R partial sums of split rows
-    const float* fac[8];       // rotated factor matrices (fac[0] unused)
-    int32_t fword[8];          // rotated field: first word,
-    int32_t fshift[8];         //   bit shift within it,
-    uint32_t fmask[8];         //   and width mask
+    const float* fac[8];       // rotated: fac[k] = factor of mode (d + k) mod N
+    int32_t rot[8];            // rot[k] = (d + k) mod N
+    int32_t foff[8];           // bit offset of each mode's index (packed layout)
+    uint32_t fmask[8];         // width mask of each mode's index (packed layout)
 };
 
 struct FixupArgs {
@@ -36,8 +38,9 @@ struct FixupArgs {
     int32_t nempty;
 };
 
-// Returns false if (nmodes, rank, words) has no compiled kernel.
-bool launch_ec(int nmodes, int rank, int words, int kappa, const EcArgs& a, hipStream_t s);
+// Returns false if (nmodes, rank, record words, layout kind) has no kernel.
+bool launch_ec(int nmodes, int rank, int words, int kind, int kappa, const EcArgs& a,
+               hipStream_t s);
 void launch_fixup(int rank, const FixupArgs& a, hipStream_t s);
 // Moves every record of the stream from position p to the position reached by
 // following `hops` next-position arrays (nxt[0] first).

@@ -256,31 +256,48 @@ std::string validate(int nmodes, const int64_t* dims, int64_t nnz, const int32_t
 
 bool choose_layout(int nmodes, const int64_t* dims, RecordLayout* lay) {
     lay->nmodes = nmodes;
-    int total = 0;
+    int packed_bits = 0;
+    bool small = true;
     for (int w = 0; w < nmodes; ++w) {
-        int b = std::max(1, bit_length(dims[w] - 1));
-        lay->bits[w] = b;
-        lay->off[w] = total;
-        total += b;
+        packed_bits += std::max(1, bit_length(dims[w] - 1));
+        small = small && dims[w] <= 65536;
     }
-    if (total <= 96)
-        lay->words = 4;
-    else if (total <= 224)
-        lay->words = 8;
+    auto set = [&](int kind, int words) {
+        lay->kind = kind;
+        lay->words = words;
+        int o = 0;
+        for (int w = 0; w < nmodes; ++w) {
+            const int b = kind == kWord32 ? 32 : kind == kHalf16 ? 16
+                                                                 : std::max(1, bit_length(dims[w] - 1));
+            lay->bits[w] = b;
+            lay->off[w] = o;
+            o += b;
+        }
+    };
+    if (nmodes <= 3)
+        set(kWord32, 4);
+    else if (small && nmodes <= 6)
+        set(kHalf16, 4);
+    else if (packed_bits <= 96 && nmodes <= 6)
+        set(kPacked, 4);
+    else if (nmodes <= 7)
+        set(kWord32, 8);
+    else if (small)
+        set(kHalf16, 8);
     else
-        return false;
-    return true;
+        set(kWord32, 12);
+    return nmodes >= 1 && nmodes <= kMaxModes;
 }
 
 void pack_record(const RecordLayout& lay, const int32_t* idx, int64_t nnz, const float* val,
                  int64_t e, uint32_t* out) {
     for (int k = 0; k < lay.words; ++k) out[k] = 0;
     for (int w = 0; w < lay.nmodes; ++w) {
-        uint32_t v = (uint32_t)idx[(int64_t)w * nnz + e];
-        int o = lay.off[w];
-        int wi = o >> 5, sh = o & 31;
-        out[wi] |= v << sh;
-        if (sh + lay.bits[w] > 32) out[wi + 1] |= v >> (32 - sh);
+        const uint64_t v = (uint32_t)idx[(int64_t)w * nnz + e];
+        const int o = lay.off[w];
+        const int wi = o >> 5, sh = o & 31;
+        out[wi] |= (uint32_t)(v << sh);
+        if (sh + lay.bits[w] > 32) out[wi + 1] |= (uint32_t)(v >> (32 - sh));
     }
     float f = val ? val[e] : 0.0f;
     std::memcpy(&out[lay.words - 1], &f, 4);
@@ -288,11 +305,11 @@ void pack_record(const RecordLayout& lay, const int32_t* idx, int64_t nnz, const
 
 void unpack_record(const RecordLayout& lay, const uint32_t* rec, int32_t* c, float* v) {
     for (int w = 0; w < lay.nmodes; ++w) {
-        int o = lay.off[w];
-        int wi = o >> 5, sh = o & 31;
-        uint64_t lo = rec[wi];
-        uint64_t hi = (wi + 1 < lay.words - 1) ? rec[wi + 1] : 0;
-        uint64_t x = ((hi << 32) | lo) >> sh;
+        const int o = lay.off[w];
+        const int wi = o >> 5, sh = o & 31;
+        const uint64_t lo = rec[wi];
+        const uint64_t hi = (wi + 1 < lay.words - 1) ? rec[wi + 1] : 0;
+        const uint64_t x = ((hi << 32) | lo) >> sh;
         c[w] = (int32_t)(x & ((uint64_t(1) << lay.bits[w]) - 1));
     }
     std::memcpy(v, &rec[lay.words - 1], 4);

@@ -10,12 +10,19 @@ namespace spt {
 
 constexpr int kMaxModes = 8;
 
-// Bit layout of one packed record <c_0..c_{N-1}, val>: the N indices are
-// packed little-endian into the first (words-1) 32-bit words, field w
-// taking bits [off[w], off[w]+bits[w]); the last word holds the FP32 value.
+// Layout of one record <c_0..c_{N-1}, val>: the indices fill words
+// 0 .. words-2, the last word holds the FP32 value.  Index w occupies bits
+// [off[w], off[w] + bits[w]) of the little-endian index words.  Kinds:
+//   kWord32  index w is word w                      (N <= words - 1)
+//   kHalf16  index w is the half-word w (dims <= 2^16)
+//   kPacked  indices packed back to back, each ceil(log2 I_w) bits, in the
+//            first 96 bits (16-byte records only)
+enum LayoutKind : int { kWord32 = 0, kHalf16 = 1, kPacked = 2 };
+
 struct RecordLayout {
     int nmodes = 0;
-    int words = 0;            // 4 (16 B) or 8 (32 B)
+    int words = 0;            // 4 (16 B), 8 (32 B) or 12 (48 B)
+    int kind = kWord32;
     int bits[kMaxModes] = {};
     int off[kMaxModes] = {};
 };
@@ -68,7 +75,8 @@ std::string validate(int nmodes, const int64_t* dims, int64_t nnz, const int32_t
 void build_plan(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
                 const float* val, const PlanOptions& opt, Plan* plan);
 
-// Chooses the record layout; returns false when the index bits exceed 224.
+// Chooses the smallest record, preferring layouts the kernels decode with
+// fixed shifts; returns false if no layout fits.
 bool choose_layout(int nmodes, const int64_t* dims, RecordLayout* lay);
 
 // Packs nonzero e into `words` 32-bit words.
