@@ -93,6 +93,7 @@ def main() -> int:
     ap.add_argument("--kappa", type=int, default=0)
     ap.add_argument("--no-ec-only", action="store_true", help="skip phase C")
     ap.add_argument("--no-als", action="store_true", help="skip phase B")
+    ap.add_argument("--no-bf16", action="store_true", help="skip phase D")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     args = ap.parse_args()
 
@@ -152,6 +153,34 @@ def main() -> int:
     canon = 4 * (2 * N + 1)
     bytes_canon = [spec.nnz * 2 * canon + sum(dims[w] for w in range(N) if w != d) * R * 4 + dims[d] * R * 4
                    for d in range(N)]
+
+    # ---- phase D: the same passes with BF16 factor gathers (FP32 accumulation)
+    bf16 = None
+    if not args.no_bf16:
+        ref = [o.clone() for o in outs]          # FP32-gather results of phase A
+        fac32 = fac
+        fac = [f.to(torch.bfloat16) for f in fac32]
+        for _ in range(W):
+            all_modes(t, True)
+        torch.cuda.synchronize()
+        S.timing_control(t, True, want=False)
+        w0 = time.perf_counter()
+        for _ in range(K):
+            all_modes(t, True)
+        torch.cuda.synchronize()
+        wall_d = (time.perf_counter() - w0) * 1e3 / K
+        tm_d = S.timing_control(t, False)
+        ec_d = [tm_d["ec_ms"][d] / max(1, tm_d["calls"][d]) for d in range(N)]
+        err = [float(torch.linalg.vector_norm(outs[d] - ref[d]) / torch.linalg.vector_norm(ref[d]))
+               for d in range(N)]
+        bytes_d = [b - (sum(dims[w] for w in range(N) if w != d) * R * 2) for d, b in enumerate(bytes_a)]
+        bf16 = {"ms_per_pass": round(wall_d, 4), "ec_remap_kernel_ms": [round(x, 4) for x in ec_d],
+                "rel_err_vs_fp32_gather": [float("%.3g" % e) for e in err],
+                "GBps": round(sum(bytes_d) / (sum(ec_d) * 1e-3) / 1e9, 1)}
+        fac = fac32
+        del ref
+        log(f"phase D: BF16 gathers {wall_d:.3f} ms per all-mode pass; kernels "
+            f"{['%.3f' % x for x in ec_d]} ms; rel err vs FP32 gathers {['%.2e' % e for e in err]}")
 
     # ---- phase B: CP-ALS sweeps
     ms_step = None
@@ -242,6 +271,7 @@ def main() -> int:
             "remap_share": round(1 - ec_only / wall_a, 4) if ec_only is not None else None,
             "canonical_record_GBps": round(sum(bytes_canon) / (sum(ec_ms) * 1e-3) / 1e9, 1),
             "fit": fit,
+            "bf16_gather": bf16,
             "prep_seconds": round(info["prep_seconds"], 2),
             "copy_GBps": round(copy_gbps, 1),
             "split_rows": info["split_rows"],

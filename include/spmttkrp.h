@@ -18,7 +18,7 @@
  *    Device work is enqueued asynchronously on it unless stated otherwise.
  *  - Indices are 0-based int32, values FP32.  Dimensions and nnz must be
  *    below 2^31; 2 <= nmodes <= 8.  Ranks 8, 16, 32, 64 and 128 are compiled.
- *  - Factor matrices are row-major I_w x R; FP32 (SPT_F32) storage.
+ *  - Factor matrices are row-major I_w x R, FP32 or BF16 (spt_dtype).
  */
 #ifndef SPMTTKRP_H
 #define SPMTTKRP_H
@@ -40,7 +40,9 @@ typedef enum spt_status {
     SPT_ERR_UNSUPPORTED = 7    /* rank / mode count / layout not compiled       */
 } spt_status;
 
-typedef enum spt_dtype { SPT_F32 = 0 } spt_dtype;
+/* Factor storage for the gathers: FP32, or BF16 (the FP32 value rounded to
+ * nearest, ties to even; 16-bit patterns).  Accumulation is FP32 either way. */
+typedef enum spt_dtype { SPT_F32 = 0, SPT_BF16 = 1 } spt_dtype;
 
 typedef struct spt_tensor_s *spt_tensor_t;  /* opaque, owned by the library */
 
@@ -109,8 +111,8 @@ spt_status spt_remap_for_mode(spt_tensor_t t, int32_t mode, void *stream);
  * spt_mttkrp -- spMTTKRP for one output mode (Eq. 1; Algorithms 2-4):
  *   out(i, r) = sum_{nonzeros e with i_mode(e) = i} val(e) *
  *               prod_{w != mode} factors[w](i_w(e), r)
- *   factors  host array of nmodes device pointers, row-major I_w x rank;
- *            factors[mode] is not read and may be NULL
+ *   factors  host array of nmodes device pointers, row-major I_w x rank,
+ *            element type fdtype; factors[mode] is not read and may be NULL
  *   rank     8, 16, 32, 64 or 128
  *   out      device float, I_mode x rank row-major; OVERWRITTEN (rows with no
  *            nonzero are set to zero)
@@ -132,7 +134,10 @@ spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void *const *factors,
  * product of the other factors' Grams (FP64); Y_d = M V^-1 via Cholesky in
  * FP64 (one ridge retry of 1e-12 tr(V)/R, else NOT_SPD); columns of Y_d
  * scaled to unit 2-norm, lambda = the norms.
- *   factors  host array of nmodes device float pointers, updated in place
+ *   factors  host array of nmodes device float pointers (FP32 always),
+ *            updated in place.  fdtype = SPT_BF16 gathers BF16 copies of them
+ *            (kept by the handle, re-rounded after every update); the solve,
+ *            Grams and fit use the FP32 factors.
  *   lambda   device double[rank], receives the column norms of the last mode
  *   fit      host double*, receives 1 - ||X - Xhat|| / ||X|| (synchronises
  *            the stream); NULL to skip
@@ -143,6 +148,26 @@ spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void *const *factors,
  */
 spt_status spt_cp_als_iter(spt_tensor_t t, void *const *factors, spt_dtype fdtype,
                            int32_t rank, double *lambda, double *fit, void *stream);
+
+/*
+ * spt_cp_gradient -- loss and gradient of the CP model fitted to the
+ * observed nonzeros only (a least-squares fit over the stored entries; the
+ * method's spMTTKRP is the adjoint):
+ *   m_e  = sum_r prod_w factors[w](i_w(e), r)           (forward, every e)
+ *   loss = 1/2 sum_e (x_e - m_e)^2                       (FP64)
+ *   grads[d] = dloss/dfactors[d] = MTTKRP of the residuals (m_e - x_e), mode d
+ * The forward kernel writes a residual stream (the records with value
+ * m_e - x_e); the adjoint is the spMTTKRP kernel over it, remapped mode to
+ * mode like the tensor itself.
+ *   factors  host array of nmodes device float pointers (I_w x rank)
+ *   grads    host array of nmodes device float pointers, overwritten
+ *   loss     device double[1], overwritten
+ * rank 8, 16, 32 or 64; FP32 factors.  The tensor's stream must be in mode
+ * 0's order (it is read, not moved).  The residual streams are allocated on
+ * first use and kept by the handle.  Errors: STATE, UNSUPPORTED, HIP, OOM.
+ */
+spt_status spt_cp_gradient(spt_tensor_t t, const void *const *factors, spt_dtype fdtype,
+                           int32_t rank, void *const *grads, double *loss, void *stream);
 
 /* spt_tensor_info -- fills *info (host). */
 spt_status spt_tensor_info(spt_tensor_t t, spt_info *info);

@@ -231,6 +231,23 @@ def plan(dims: Sequence[int], idx: np.ndarray, kappa: int,
 
 
 # ---------------------------------------------------------------------------
+# BF16 storage of factors (the precision direction; the paper is silent)
+# ---------------------------------------------------------------------------
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """FP32 values rounded to BF16 (8-bit exponent, 7-bit fraction) to nearest,
+    ties to even, returned widened back to FP32 exactly.  Defined on the bit
+    pattern: the lower 16 bits are dropped after adding half an ulp of the
+    kept part (0x7FFF plus the lowest kept bit); NaNs stay NaN."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    nan = (u & 0x7F800000) == 0x7F800000
+    nan &= (u & 0x007FFFFF) != 0
+    r = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    r = np.where(nan, (u & 0xFFFF0000) | 0x00400000, r)
+    return r.astype(np.uint32).view(np.float32).reshape(np.shape(x))
+
+
+# ---------------------------------------------------------------------------
 # CP-ALS and fit (textbook; the paper only names the method)
 # ---------------------------------------------------------------------------
 
@@ -299,10 +316,13 @@ def fit_from(normX2: float, M_last: np.ndarray, Y_last: np.ndarray,
 
 
 def cp_als(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
-           factors: Sequence[np.ndarray], iters: int):
+           factors: Sequence[np.ndarray], iters: int, gather=None):
     """Fixed-count CP-ALS in FP64, modes updated in the order 0..N-1.
 
-    Returns (factors, lam, fits) with one fit per completed iteration.
+    gather: optional map applied to each factor before it enters MTTKRP
+    (e.g. storage rounding of the gathered copies); the solve, Grams and fit
+    use the unrounded factors.  Returns (factors, lam, fits) with one fit per
+    completed iteration.
     """
     N = len(dims)
     Y = [np.asarray(f, dtype=np.float64).copy() for f in factors]
@@ -313,11 +333,43 @@ def cp_als(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
     for _ in range(iters):
         M = None
         for d in range(N):
-            M = mttkrp(dims, idx, val, Y, d)
+            G = Y if gather is None else [gather(y) for y in Y]
+            M = mttkrp(dims, idx, val, G, d)
             Y[d], lam = als_update(M, grams, d)
             grams[d] = Y[d].T @ Y[d]
         fits.append(fit_from(normX2, M, Y[N - 1], lam, grams))
     return Y, lam, fits
+
+
+# ---------------------------------------------------------------------------
+# Gradient of the CP fit over the observed nonzeros (the differentiation
+# direction; the adjoint of the model at the nonzeros is an MTTKRP, Eq. (1))
+# ---------------------------------------------------------------------------
+
+def model_at(idx: np.ndarray, factors: Sequence[np.ndarray]) -> np.ndarray:
+    """m_e = sum_r prod_w Y_w(i_w(e), r) at every nonzero, FP64."""
+    nnz = idx.shape[1]
+    out = np.empty(nnz, dtype=np.float64)
+    f64 = [np.asarray(f, dtype=np.float64) for f in factors]
+    step = 1 << 20
+    for a in range(0, nnz, step):
+        b = min(nnz, a + step)
+        p = np.ones((b - a, f64[0].shape[1]))
+        for w, f in enumerate(f64):
+            p *= f[idx[w, a:b]]
+        out[a:b] = p.sum(axis=1)
+    return out
+
+
+def cp_loss_grad(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
+                 factors: Sequence[np.ndarray]):
+    """loss = 1/2 sum_e (x_e - m_e)^2 and d loss / d Y_d = MTTKRP of the
+    residuals (m_e - x_e) for every mode d, all in FP64."""
+    m = model_at(idx, factors)
+    r = m - np.asarray(val, dtype=np.float64)
+    loss = 0.5 * float(np.dot(r, r))
+    grads = [mttkrp(dims, idx, r, factors, d) for d in range(len(dims))]
+    return loss, grads
 
 
 def full_tensor(dims: Sequence[int], idx: np.ndarray, val: np.ndarray) -> np.ndarray:

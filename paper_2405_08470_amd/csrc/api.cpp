@@ -79,6 +79,9 @@ struct spt_tensor_s {
     double* gpart = nullptr;
     double* ipart = nullptr;
     double* Vinv = nullptr;
+    uint16_t* shadow[8] = {};  // BF16 copies of the factors (CP-ALS with SPT_BF16)
+    uint32_t* res[2] = {nullptr, nullptr};  // residual stream + its remap target
+    double* loss_part = nullptr;
     double* Gsum = nullptr;
     double* Isum = nullptr;
     double* fitd = nullptr;
@@ -165,6 +168,9 @@ spt_status ensure_carry(spt_tensor_s* t, int rank) {
         if ((st = dalloc(t, &t->ipart, (size_t)(nb * rank), &t->ws_allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->Vinv, (size_t)E, &t->ws_allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->Gsum, (size_t)E, &t->ws_allocs)) != SPT_OK) return st;
+        for (int w = 0; w < t->N; ++w)
+            if ((st = dalloc(t, &t->shadow[w], (size_t)(t->dims[w] * rank), &t->ws_allocs)) != SPT_OK)
+                return st;
         if ((st = dalloc(t, &t->Isum, (size_t)rank, &t->ws_allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->fitd, 1, &t->ws_allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->status, 1, &t->ws_allocs)) != SPT_OK) return st;
@@ -187,22 +193,17 @@ hipEvent_t mark(spt_tensor_s* t, hipStream_t s) {
     return e;
 }
 
-// mode d's stream buffer and, when remapping, the target buffer
-spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int rank, float* out,
-                      bool fuse, hipStream_t s) {
+// EC (+ remap into rec_out when it is not null) and fixup for one mode over
+// the stream rec_in, which must be in that mode's order.
+spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32_t* rec_out,
+                       const void* const* factors, int fdtype, int rank, float* out, hipStream_t s) {
     spt_status st = ensure_carry(t, rank);
     if (st != SPT_OK) return st;
     const int N = t->N;
     spt::EcArgs a{};
-    if (t->copies) {
-        a.rec_in = t->rec_mode[mode];
-        a.rec_out = nullptr;
-        a.nxt = nullptr;
-    } else {
-        a.rec_in = t->rec[t->cur];
-        a.rec_out = fuse ? t->rec[1 - t->cur] : nullptr;
-        a.nxt = fuse ? t->nxt[mode] : nullptr;
-    }
+    a.rec_in = rec_in;
+    a.rec_out = rec_out;
+    a.nxt = rec_out ? t->nxt[mode] : nullptr;
     a.ptr = t->ptr[mode];
     a.psplit_ptr = t->psplit_ptr[mode];
     a.psplit_row = t->psplit_row[mode];
@@ -211,14 +212,14 @@ spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int
     a.carry = t->carry;
     for (int k = 0; k < N; ++k) {
         const int w = (mode + k) % N;
-        a.fac[k] = (const float*)factors[w];
+        a.fac[k] = factors[w];
         a.rot[k] = w;
         a.foff[k] = t->lay.off[k];
         a.fmask[k] = (uint32_t)((uint64_t(1) << t->lay.bits[k]) - 1);
     }
     spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr}};
     tm.ev[0] = mark(t, s);
-    if (!spt::launch_ec(N, rank, t->lay.words, t->lay.kind, t->kappa, a, s))
+    if (!spt::launch_ec(N, rank, fdtype, t->lay.words, t->lay.kind, t->kappa, a, s))
         return fail(SPT_ERR_UNSUPPORTED, "no kernel compiled for this mode count / rank / record size");
     HIPCHK(hipGetLastError());
     tm.ev[1] = mark(t, s);
@@ -234,10 +235,41 @@ spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int
     HIPCHK(hipGetLastError());
     tm.ev[2] = mark(t, s);
     if (t->timing && tm.ev[0] && tm.ev[1] && tm.ev[2]) t->timed.push_back(tm);
-    if (fuse && !t->copies) {
+    return SPT_OK;
+}
+
+// mode d's stream and, when remapping, the target buffer of the tensor
+spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int fdtype, int rank,
+                      float* out, bool fuse, hipStream_t s) {
+    if (t->copies)
+        return launch_mode(t, mode, t->rec_mode[mode], nullptr, factors, fdtype, rank, out, s);
+    spt_status st = launch_mode(t, mode, t->rec[t->cur], fuse ? t->rec[1 - t->cur] : nullptr,
+                                factors, fdtype, rank, out, s);
+    if (st != SPT_OK) return st;
+    if (fuse) {
         t->cur = 1 - t->cur;
-        t->cur_mode = (mode + 1) % N;
+        t->cur_mode = (mode + 1) % t->N;
     }
+    return SPT_OK;
+}
+
+// Forward pass over `rec_in` (in any mode's order): residual records into
+// `rec_res`, loss partials into t->loss_part.
+spt_status launch_forward_pass(spt_tensor_s* t, const uint32_t* rec_in, uint32_t* rec_res,
+                               const void* const* factors, int rank, hipStream_t s) {
+    spt::ForwardArgs f{};
+    f.rec_in = rec_in;
+    f.rec_res = rec_res;
+    for (int w = 0; w < t->N; ++w) {
+        f.fac[w] = (const float*)factors[w];
+        f.foff[w] = t->lay.off[w];
+        f.fmask[w] = (uint32_t)((uint64_t(1) << t->lay.bits[w]) - 1);
+    }
+    f.loss_part = t->loss_part;
+    f.nnz = t->nnz;
+    if (!spt::launch_forward(t->N, rank, t->lay.words, t->lay.kind, f, s))
+        return fail(SPT_ERR_UNSUPPORTED, "no forward kernel for this mode count / rank / layout");
+    HIPCHK(hipGetLastError());
     return SPT_OK;
 }
 
@@ -473,7 +505,7 @@ spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void* const* factors, 
     g_last_error.clear();
     if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
     if (mode < 0 || mode >= t->N) return fail(SPT_ERR_INVALID_ARG, "mode out of range");
-    if (fdtype != SPT_F32) return fail(SPT_ERR_UNSUPPORTED, "factor dtype not supported");
+    if (fdtype != SPT_F32 && fdtype != SPT_BF16) return fail(SPT_ERR_UNSUPPORTED, "factor dtype not supported");
     if (!rank_compiled(rank)) return fail(SPT_ERR_UNSUPPORTED, "rank must be 8, 16, 32, 64 or 128");
     if (!factors || !out) return fail(SPT_ERR_INVALID_ARG, "NULL factors or out");
     for (int w = 0; w < t->N; ++w)
@@ -487,14 +519,14 @@ spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void* const* factors, 
         spt_status st = do_remap(t, mode, s);
         if (st != SPT_OK) return st;
     }
-    return run_mttkrp(t, mode, factors, rank, out, (flags & SPT_FUSE_REMAP_NEXT) != 0, s);
+    return run_mttkrp(t, mode, factors, fdtype, rank, out, (flags & SPT_FUSE_REMAP_NEXT) != 0, s);
 }
 
 spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtype, int32_t rank,
                            double* lambda, double* fit, void* stream) {
     g_last_error.clear();
     if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
-    if (fdtype != SPT_F32) return fail(SPT_ERR_UNSUPPORTED, "factor dtype not supported");
+    if (fdtype != SPT_F32 && fdtype != SPT_BF16) return fail(SPT_ERR_UNSUPPORTED, "factor dtype not supported");
     if (!als_rank(rank)) return fail(SPT_ERR_UNSUPPORTED, "CP-ALS rank must be 8, 16, 32 or 64");
     if (!factors || !lambda) return fail(SPT_ERR_INVALID_ARG, "NULL factors or lambda");
     for (int w = 0; w < t->N; ++w)
@@ -526,8 +558,14 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
         spt::launch_reduce_partials(t->gpart, nb, (int)E, t->grams + w * E, s);
     }
     HIPCHK(hipGetLastError());
+    const bool bf16 = fdtype == SPT_BF16;
+    const void* gath[8];
+    for (int w = 0; w < N; ++w) {
+        gath[w] = bf16 ? (const void*)t->shadow[w] : (const void*)factors[w];
+        if (bf16) spt::launch_to_bf16((const float*)factors[w], t->shadow[w], t->dims[w] * rank, s);
+    }
     for (int d = 0; d < N; ++d) {
-        st = run_mttkrp(t, d, (const void* const*)factors, rank, t->M, true, s);
+        st = run_mttkrp(t, d, gath, fdtype, rank, t->M, true, s);
         if (st != SPT_OK) return st;
         spt::launch_normal_inverse(rank, N, d, t->grams, t->Vinv, t->status, s);
         const int nb = spt::solve_blocks(t->dims[d]);
@@ -538,6 +576,7 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
         spt::launch_als_finish(rank, N, d, t->Gsum, t->Isum, t->grams, lambda, t->norm_sq,
                                (fit && d == N - 1) ? 1 : 0, t->fitd, s);
         spt::launch_scale_cols(rank, (float*)factors[d], t->dims[d], lambda, s);
+        if (bf16) spt::launch_to_bf16((const float*)factors[d], t->shadow[d], t->dims[d] * rank, s);
         HIPCHK(hipGetLastError());
         if (t->timing && !t->timed.empty() && t->timed.back().mode == d && !t->timed.back().ev[3])
             t->timed.back().ev[3] = mark(t, s);
@@ -555,6 +594,54 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
             t->status_host[0] = 0;
             return fail(SPT_ERR_NOT_SPD, "normal matrix not positive definite");
         }
+    }
+    return SPT_OK;
+}
+
+spt_status spt_cp_gradient(spt_tensor_t t, const void* const* factors, spt_dtype fdtype,
+                           int32_t rank, void* const* grads, double* loss, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
+    if (fdtype != SPT_F32) return fail(SPT_ERR_UNSUPPORTED, "gradient supports FP32 factors");
+    if (!als_rank(rank)) return fail(SPT_ERR_UNSUPPORTED, "gradient rank must be 8, 16, 32 or 64");
+    if (!factors || !grads || !loss) return fail(SPT_ERR_INVALID_ARG, "NULL factors, grads or loss");
+    for (int w = 0; w < t->N; ++w)
+        if (!factors[w] || !grads[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor or gradient");
+    if (!t->copies && t->cur_mode != 0) return fail(SPT_ERR_STATE, "stream must be in mode 0's order");
+    hipStream_t s = (hipStream_t)stream;
+    spt_status st = ensure_carry(t, rank);
+    if (st != SPT_OK) return st;
+    const int W = t->lay.words;
+    if (!t->res[0]) {
+        const int nres = t->copies ? 1 : 2;
+        for (int k = 0; k < nres; ++k)
+            if ((st = dalloc(t, &t->res[k], (size_t)(t->nnz * W), &t->allocs)) != SPT_OK) return st;
+        if ((st = dalloc(t, &t->loss_part, (size_t)spt::forward_blocks(t->nnz), &t->allocs)) != SPT_OK)
+            return st;
+    }
+    const int N = t->N;
+    const int nb = spt::forward_blocks(t->nnz);
+    if (t->copies) {
+        // each mode's own stream: residuals in that order, then its MTTKRP
+        for (int d = 0; d < N; ++d) {
+            if ((st = launch_forward_pass(t, t->rec_mode[d], t->res[0], factors, rank, s)) != SPT_OK)
+                return st;
+            if (d == 0) spt::launch_reduce_partials(t->loss_part, nb, 1, loss, s);
+            if ((st = launch_mode(t, d, t->res[0], nullptr, factors, SPT_F32, rank, (float*)grads[d], s)) != SPT_OK)
+                return st;
+        }
+        return SPT_OK;
+    }
+    // residual stream in mode 0's order, then the adjoint MTTKRP of every mode
+    // with the residual stream remapped from mode to mode (back to mode 0)
+    if ((st = launch_forward_pass(t, t->rec[t->cur], t->res[0], factors, rank, s)) != SPT_OK) return st;
+    spt::launch_reduce_partials(t->loss_part, nb, 1, loss, s);
+    int cur = 0;
+    for (int d = 0; d < N; ++d) {
+        if ((st = launch_mode(t, d, t->res[cur], t->res[1 - cur], factors, SPT_F32, rank,
+                              (float*)grads[d], s)) != SPT_OK)
+            return st;
+        cur = 1 - cur;
     }
     return SPT_OK;
 }

@@ -92,9 +92,126 @@ __device__ __forceinline__ float* row_dst(const EcArgs& a, int row, int slot) {
     return slot >= 0 ? a.carry + (int64_t)slot * R : a.out + (int64_t)row * R;
 }
 
-template <int N, int R, int RW, int KIND>
+// Factor element types.  A lane loads 16 bytes of a factor row at a time:
+// 4 FP32 values, or 8 BF16 values (raw 16-bit patterns, widened exactly).
+struct FacF32 {
+    static constexpr int kPerLoad = 4;
+    static constexpr int kBytes = 4;
+};
+struct FacBF16 {
+    static constexpr int kPerLoad = 8;
+    static constexpr int kBytes = 2;
+};
+
+template <typename FT>
+__device__ __forceinline__ void widen(const uint4& u, float (&f)[FT::kPerLoad]) {
+    if constexpr (FT::kPerLoad == 4) {
+        f[0] = __uint_as_float(u.x);
+        f[1] = __uint_as_float(u.y);
+        f[2] = __uint_as_float(u.z);
+        f[3] = __uint_as_float(u.w);
+    } else {
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f[2 * i] = __uint_as_float(w[i] << 16);
+            f[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_vals(float* dst, const float (&v)[V]) {
+#pragma unroll
+    for (int i = 0; i < V; i += 4)
+        *reinterpret_cast<float4*>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+}
+
+// The body of one step of ec_kernel (see there); a macro rather than a
+// lambda so the per-group state stays in registers.
+#define SPT_EC_STEP(T_ARG, cur, ncur, nxt_rec, nnext) \
+    do { \
+        const int t = (T_ARG); \
+        if (t + li < gn) { \
+            if (remap) store_rec<RW>(a.rec_out, ncur, cur); \
+            decode_all<RW, KIND>(cur, a, stage, lane, seq); \
+            stage[N][lane] = rword<RW - 1, RW>(cur); \
+            stage[N + 1][lane] = (uint32_t)slot_of((int)stage[mode][lane]); \
+        } \
+        __syncthreads(); \
+        const int cnt = gn - t; \
+        _Pragma("unroll") \
+        for (int kb = 0; kb < L; kb += B) { \
+            uint4 y[B][NG]; \
+        _Pragma("unroll") \
+            for (int b = 0; b < B; ++b) { \
+                const int slot = g * L + kb + b; \
+                const bool live = kb + b < cnt; \
+        _Pragma("unroll") \
+                for (int k = 0; k < NG; ++k) { \
+                    const uint32_t cprev = b == 0 ? last_c[k] : cb[b - 1][k]; \
+                    const uint32_t c = live ? stage[a.rot[k + 1]][slot] : cprev; \
+                    cb[b][k] = c; \
+                    y[b][k] = b == 0 ? last_y[k] : y[b - 1][k]; \
+                    if (c != cprev) \
+                        y[b][k] = *reinterpret_cast<const uint4*>( \
+                            static_cast<const char*>(a.fac[k + 1]) + \
+                            ((int64_t)c * R + li * V) * FT::kBytes); \
+                } \
+            } \
+            if (kb == 0 && t + L + li < gn) { \
+                load_rec<RW>(a.rec_in, gs + t + L + li, nxt_rec); \
+                if (remap) nnext = a.nxt[gs + t + L + li]; \
+            } \
+        _Pragma("unroll") \
+            for (int b = 0; b < B; ++b) { \
+                if (kb + b < cnt) { \
+                    const int slot = g * L + kb + b; \
+                    const int row = (int)stage[mode][slot]; \
+                    if (row != cur_row) { \
+                        if (cur_row >= 0) { \
+                            if (first_seg && open_left) { \
+                                store_vals<V>(&part[0][g][li * V], acc); \
+                                if (li == 0) { \
+                                    prow[0][g] = cur_row; \
+                                    pslot[0][g] = cur_slot; \
+                                } \
+                            } else { \
+                                store_vals<V>(row_dst<R>(a, cur_row, cur_slot) + li * V, acc); \
+                            } \
+                            first_seg = false; \
+                        } \
+                        cur_row = row; \
+                        cur_slot = (int)stage[N + 1][slot]; \
+        _Pragma("unroll") \
+                        for (int v = 0; v < V; ++v) acc[v] = 0.0f; \
+                    } \
+                    const float val = __uint_as_float(stage[N][slot]); \
+                    float prod[V]; \
+                    widen<FT>(y[b][0], prod); \
+        _Pragma("unroll") \
+                    for (int k = 1; k < NG; ++k) { \
+                        float f[V]; \
+                        widen<FT>(y[b][k], f); \
+        _Pragma("unroll") \
+                        for (int v = 0; v < V; ++v) prod[v] *= f[v]; \
+                    } \
+        _Pragma("unroll") \
+                    for (int v = 0; v < V; ++v) acc[v] = fmaf(prod[v], val, acc[v]); \
+                } \
+            } \
+        _Pragma("unroll") \
+            for (int k = 0; k < NG; ++k) { \
+                last_c[k] = cb[B - 1][k]; \
+                last_y[k] = y[B - 1][k]; \
+            } \
+        } \
+        __syncthreads(); \
+    } while (0)
+
+template <int N, int R, int RW, int KIND, typename FT>
 __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
-    constexpr int V = 4;
+    constexpr int V = FT::kPerLoad;
     constexpr int L = R / V;     // lanes per nonzero
     constexpr int G = 64 / L;    // lane groups = nonzeros in flight
     constexpr int NG = N - 1;    // gathered factor rows per nonzero
@@ -102,7 +219,7 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     // with at most SPT_GATHER_INFLIGHT float4 gathers in flight per lane
     constexpr int BMAX = (SPT_GATHER_INFLIGHT / NG) > 0 ? SPT_GATHER_INFLIGHT / NG : 1;
     constexpr int B = L <= BMAX ? L : (L / 2 <= BMAX ? L / 2 : (L / 4 <= BMAX ? L / 4 : (L / 8 <= BMAX ? L / 8 : 1)));
-    static_assert(R % V == 0 && 64 % L == 0 && L % B == 0, "rank");
+    static_assert(R % V == 0 && L >= 1 && 64 % L == 0 && L % B == 0, "rank");
     // staged words per nonzero: indices in mode order, value, carry slot
     constexpr int SW = N + 2;
     constexpr int MAXSPLIT = 64;  // split rows of a partition kept in LDS
@@ -167,6 +284,16 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     const int steps = (int)(q + (rm > 0 ? 1 : 0));
     const bool remap = a.rec_out != nullptr;
 
+    // factor rows gathered for the group's previous nonzero
+    uint32_t last_c[NG];
+    uint4 last_y[NG];
+    uint32_t cb[B][NG];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+        last_c[k] = 0xFFFFFFFFu;
+        last_y[k] = make_uint4(0u, 0u, 0u, 0u);
+    }
+
     // carry slot of a row of this partition (-1: not a split row)
     auto slot_of = [&](int row) {
         int slot = -1;
@@ -179,84 +306,12 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
         return slot;
     };
 
-    // One step: commit the record fetched for this step (remap store,
-    // decode), prefetch the next step's record into the other buffer, then
-    // run the lane groups over their L nonzeros of this step.
-    auto step = [&](int t, Rec<RW>& cur, int32_t& ncur, Rec<RW>& nxt_rec, int32_t& nnext) {
-        if (t + li < gn) {
-            if (remap) store_rec<RW>(a.rec_out, ncur, cur);
-            decode_all<RW, KIND>(cur, a, stage, lane, seq);
-            stage[N][lane] = rword<RW - 1, RW>(cur);
-            stage[N + 1][lane] = (uint32_t)slot_of((int)stage[mode][lane]);
-        }
-        __syncthreads();
-        const int cnt = gn - t;
-#pragma unroll
-        for (int kb = 0; kb < L; kb += B) {
-            float4 y[B][NG];
-            // issue every gather of the batch first
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if (kb + b < cnt) {
-                    const int slot = g * L + kb + b;
-#pragma unroll
-                    for (int k = 0; k < NG; ++k)
-                        y[b][k] = *reinterpret_cast<const float4*>(
-                            a.fac[k + 1] + (int64_t)stage[a.rot[k + 1]][slot] * R + li * V);
-                }
-            }
-            if (kb == 0 && t + L + li < gn) {
-                // after the first gathers, so waiting for those does not wait
-                // for this (memory counters retire in issue order)
-                load_rec<RW>(a.rec_in, gs + t + L + li, nxt_rec);
-                if (remap) nnext = a.nxt[gs + t + L + li];
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if (kb + b < cnt) {
-                    const int slot = g * L + kb + b;
-                    const int row = (int)stage[mode][slot];
-                    if (row != cur_row) {
-                        if (cur_row >= 0) {
-                            if (first_seg && open_left) {
-#pragma unroll
-                                for (int v = 0; v < V; ++v) part[0][g][li * V + v] = acc[v];
-                                if (li == 0) {
-                                    prow[0][g] = cur_row;
-                                    pslot[0][g] = cur_slot;
-                                }
-                            } else {
-                                *reinterpret_cast<float4*>(row_dst<R>(a, cur_row, cur_slot) + li * V) =
-                                    make_float4(acc[0], acc[1], acc[2], acc[3]);
-                            }
-                            first_seg = false;
-                        }
-                        cur_row = row;
-                        cur_slot = (int)stage[N + 1][slot];
-#pragma unroll
-                        for (int v = 0; v < V; ++v) acc[v] = 0.0f;
-                    }
-                    const float val = __uint_as_float(stage[N][slot]);
-                    float4 prod = y[b][0];
-#pragma unroll
-                    for (int k = 1; k < NG; ++k) {
-                        prod.x *= y[b][k].x;
-                        prod.y *= y[b][k].y;
-                        prod.z *= y[b][k].z;
-                        prod.w *= y[b][k].w;
-                    }
-                    acc[0] = fmaf(prod.x, val, acc[0]);
-                    acc[1] = fmaf(prod.y, val, acc[1]);
-                    acc[2] = fmaf(prod.z, val, acc[2]);
-                    acc[3] = fmaf(prod.w, val, acc[3]);
-                }
-            }
-        }
-        __syncthreads();
-    };
-
-    // two record buffers, alternating, so a prefetch never overwrites the
-    // registers of a remap store still in flight
+    // One step (SPT_EC_STEP, defined above the kernel): commit the record
+    // fetched for this step (remap store, decode), prefetch the next step's
+    // record into the other buffer after the first gathers, then run the lane
+    // groups over their L nonzeros of this step.  Two record buffers
+    // alternate, so a prefetch never overwrites the registers of a remap
+    // store still in flight.
     Rec<RW> ra, rb;
     int32_t na = 0, nb = 0;
     if (li < gn) {
@@ -264,22 +319,20 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
         if (remap) na = a.nxt[gs + li];
     }
     for (int t = 0; t < steps; t += 2 * L) {
-        step(t, ra, na, rb, nb);
-        if (t + L < steps) step(t + L, rb, nb, ra, na);
+        SPT_EC_STEP(t, ra, na, rb, nb);
+        if (t + L < steps) SPT_EC_STEP(t + L, rb, nb, ra, na);
     }
 
     // the group's last segment
     if (cur_row >= 0) {
         if (open_right || (first_seg && open_left)) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) part[1][g][li * V + v] = acc[v];
+            store_vals<V>(&part[1][g][li * V], acc);
             if (li == 0) {
                 prow[1][g] = cur_row;
                 pslot[1][g] = cur_slot;
             }
         } else {
-            *reinterpret_cast<float4*>(row_dst<R>(a, cur_row, cur_slot) + li * V) =
-                make_float4(acc[0], acc[1], acc[2], acc[3]);
+            store_vals<V>(row_dst<R>(a, cur_row, cur_slot) + li * V, acc);
         }
     }
     __syncthreads();
@@ -372,6 +425,21 @@ struct NxtChain {
     const int32_t* nxt[8];
 };
 
+// FP32 -> BF16 by rounding the bit pattern to nearest, ties to even (add
+// 0x7FFF plus the lowest kept bit, truncate); NaNs stay quiet NaNs.
+__global__ void to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t u = __float_as_uint(src[i]);
+        if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) {
+            dst[i] = (uint16_t)((u >> 16) | 0x0040u);
+        } else {
+            u += 0x7FFFu + ((u >> 16) & 1u);
+            dst[i] = (uint16_t)(u >> 16);
+        }
+    }
+}
+
 template <int RW>
 __global__ void remap_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                              int64_t nnz, NxtChain ch, int hops) {
@@ -386,48 +454,61 @@ __global__ void remap_kernel(const uint32_t* __restrict__ in, uint32_t* __restri
 }
 
 template <int N, int RW, int KIND>
-bool by_rank(int rank, int kappa, const EcArgs& a, hipStream_t s) {
+bool by_rank(int rank, int fdtype, int kappa, const EcArgs& a, hipStream_t s) {
     const dim3 grid(kappa), block(64);
+    if (fdtype == 0) {
+        switch (rank) {
+            case 8: hipLaunchKernelGGL((ec_kernel<N, 8, RW, KIND, FacF32>), grid, block, 0, s, a); return true;
+            case 16: hipLaunchKernelGGL((ec_kernel<N, 16, RW, KIND, FacF32>), grid, block, 0, s, a); return true;
+            case 32: hipLaunchKernelGGL((ec_kernel<N, 32, RW, KIND, FacF32>), grid, block, 0, s, a); return true;
+            case 64: hipLaunchKernelGGL((ec_kernel<N, 64, RW, KIND, FacF32>), grid, block, 0, s, a); return true;
+            case 128: hipLaunchKernelGGL((ec_kernel<N, 128, RW, KIND, FacF32>), grid, block, 0, s, a); return true;
+            default: return false;
+        }
+    }
     switch (rank) {
-        case 8: hipLaunchKernelGGL((ec_kernel<N, 8, RW, KIND>), grid, block, 0, s, a); return true;
-        case 16: hipLaunchKernelGGL((ec_kernel<N, 16, RW, KIND>), grid, block, 0, s, a); return true;
-        case 32: hipLaunchKernelGGL((ec_kernel<N, 32, RW, KIND>), grid, block, 0, s, a); return true;
-        case 64: hipLaunchKernelGGL((ec_kernel<N, 64, RW, KIND>), grid, block, 0, s, a); return true;
-        case 128: hipLaunchKernelGGL((ec_kernel<N, 128, RW, KIND>), grid, block, 0, s, a); return true;
+        case 8: hipLaunchKernelGGL((ec_kernel<N, 8, RW, KIND, FacBF16>), grid, block, 0, s, a); return true;
+        case 16: hipLaunchKernelGGL((ec_kernel<N, 16, RW, KIND, FacBF16>), grid, block, 0, s, a); return true;
+        case 32: hipLaunchKernelGGL((ec_kernel<N, 32, RW, KIND, FacBF16>), grid, block, 0, s, a); return true;
+        case 64: hipLaunchKernelGGL((ec_kernel<N, 64, RW, KIND, FacBF16>), grid, block, 0, s, a); return true;
+        case 128: hipLaunchKernelGGL((ec_kernel<N, 128, RW, KIND, FacBF16>), grid, block, 0, s, a); return true;
         default: return false;
     }
 }
 
 // (record words, layout kind) pairs the planner can choose for N modes
 template <int N>
-bool by_layout(int rank, int words, int kind, int kappa, const EcArgs& a, hipStream_t s) {
+bool by_layout(int rank, int fdtype, int words, int kind, int kappa, const EcArgs& a,
+               hipStream_t s) {
     if constexpr (N <= 3) {
-        if (words == 4 && kind == kWord32) return by_rank<N, 4, kWord32>(rank, kappa, a, s);
+        if (words == 4 && kind == kWord32) return by_rank<N, 4, kWord32>(rank, fdtype, kappa, a, s);
     } else if constexpr (N <= 6) {
-        if (words == 4 && kind == kHalf16) return by_rank<N, 4, kHalf16>(rank, kappa, a, s);
-        if (words == 4 && kind == kPacked) return by_rank<N, 4, kPacked>(rank, kappa, a, s);
-        if (words == 8 && kind == kWord32) return by_rank<N, 8, kWord32>(rank, kappa, a, s);
+        if (words == 4 && kind == kHalf16) return by_rank<N, 4, kHalf16>(rank, fdtype, kappa, a, s);
+        if (words == 4 && kind == kPacked) return by_rank<N, 4, kPacked>(rank, fdtype, kappa, a, s);
+        if (words == 8 && kind == kWord32) return by_rank<N, 8, kWord32>(rank, fdtype, kappa, a, s);
     } else if constexpr (N == 7) {
-        if (words == 8 && kind == kWord32) return by_rank<N, 8, kWord32>(rank, kappa, a, s);
+        if (words == 8 && kind == kWord32) return by_rank<N, 8, kWord32>(rank, fdtype, kappa, a, s);
     } else {
-        if (words == 8 && kind == kHalf16) return by_rank<N, 8, kHalf16>(rank, kappa, a, s);
-        if (words == 12 && kind == kWord32) return by_rank<N, 12, kWord32>(rank, kappa, a, s);
+        if (words == 8 && kind == kHalf16) return by_rank<N, 8, kHalf16>(rank, fdtype, kappa, a, s);
+        if (words == 12 && kind == kWord32) return by_rank<N, 12, kWord32>(rank, fdtype, kappa, a, s);
     }
     return false;
 }
 
+#undef SPT_EC_STEP
+
 }  // namespace
 
-bool launch_ec(int nmodes, int rank, int words, int kind, int kappa, const EcArgs& a,
+bool launch_ec(int nmodes, int rank, int fdtype, int words, int kind, int kappa, const EcArgs& a,
                hipStream_t s) {
     switch (nmodes) {
-        case 2: return by_layout<2>(rank, words, kind, kappa, a, s);
-        case 3: return by_layout<3>(rank, words, kind, kappa, a, s);
-        case 4: return by_layout<4>(rank, words, kind, kappa, a, s);
-        case 5: return by_layout<5>(rank, words, kind, kappa, a, s);
-        case 6: return by_layout<6>(rank, words, kind, kappa, a, s);
-        case 7: return by_layout<7>(rank, words, kind, kappa, a, s);
-        case 8: return by_layout<8>(rank, words, kind, kappa, a, s);
+        case 2: return by_layout<2>(rank, fdtype, words, kind, kappa, a, s);
+        case 3: return by_layout<3>(rank, fdtype, words, kind, kappa, a, s);
+        case 4: return by_layout<4>(rank, fdtype, words, kind, kappa, a, s);
+        case 5: return by_layout<5>(rank, fdtype, words, kind, kappa, a, s);
+        case 6: return by_layout<6>(rank, fdtype, words, kind, kappa, a, s);
+        case 7: return by_layout<7>(rank, fdtype, words, kind, kappa, a, s);
+        case 8: return by_layout<8>(rank, fdtype, words, kind, kappa, a, s);
         default: return false;
     }
 }
@@ -445,6 +526,12 @@ void launch_fixup(int rank, const FixupArgs& a, hipStream_t s) {
         case 128: hipLaunchKernelGGL(fixup_kernel<128>, dim3(blocks), dim3(1024), 0, s, a, zero_blocks); break;
         default: break;
     }
+}
+
+void launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
 }
 
 void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,

@@ -22,10 +22,21 @@ struct EcArgs {
     const int32_t* psplit_slot;
     float* out;                // I_d x R
     float* carry;              // nslots x R partial sums of split rows
-    const float* fac[8];       // rotated: fac[k] = factor of mode (d + k) mod N
+    const void* fac[8];        // rotated: fac[k] = factor of mode (d + k) mod N
     int32_t rot[8];            // rot[k] = (d + k) mod N
     int32_t foff[8];           // bit offset of each mode's index (packed layout)
     uint32_t fmask[8];         // width mask of each mode's index (packed layout)
+};
+
+// Forward pass of the gradient fit (grad_kernel.hip).
+struct ForwardArgs {
+    const uint32_t* rec_in;    // records of a stream
+    uint32_t* rec_res;         // same records with value m_e - x_e, same order
+    const float* fac[8];       // factors in mode order
+    double* loss_part;         // [forward_blocks(nnz)] partial sums of (x-m)^2 / 2
+    int64_t nnz;
+    int32_t foff[8];           // bit offset of each mode's index (packed layout)
+    uint32_t fmask[8];
 };
 
 struct FixupArgs {
@@ -38,9 +49,15 @@ struct FixupArgs {
     int32_t nempty;
 };
 
-// Returns false if (nmodes, rank, record words, layout kind) has no kernel.
-bool launch_ec(int nmodes, int rank, int words, int kind, int kappa, const EcArgs& a,
+// fdtype 0: FP32 factors, 1: BF16 factors.  Returns false if the combination
+// (nmodes, rank, factor type, record words, layout kind) has no kernel.
+bool launch_ec(int nmodes, int rank, int fdtype, int words, int kind, int kappa, const EcArgs& a,
                hipStream_t s);
+int forward_blocks(int64_t nnz);
+bool launch_forward(int nmodes, int rank, int words, int kind, const ForwardArgs& a,
+                    hipStream_t s);
+// dst[i] = src[i] rounded to the nearest BF16 (ties to even), i < n
+void launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t s);
 void launch_fixup(int rank, const FixupArgs& a, hipStream_t s);
 // Moves every record of the stream from position p to the position reached by
 // following `hops` next-position arrays (nxt[0] first).

@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SPT_LIBRARY") or os.path.join(_HERE, "libspmttkrp.so")
 
 F32 = 0
+BF16 = 1
 FUSE_REMAP_NEXT = 1
 AUTO_REMAP = 2
 
@@ -54,7 +55,7 @@ class spt_timing(ctypes.Structure):
 
 
 EXPORTS = ["spt_tensor_load_coo", "spt_remap_for_mode", "spt_mttkrp", "spt_cp_als_iter",
-           "spt_tensor_info", "spt_tensor_get_remap", "spt_tensor_get_records",
+           "spt_cp_gradient", "spt_tensor_info", "spt_tensor_get_remap", "spt_tensor_get_records",
            "spt_timing_control", "spt_tensor_free", "spt_plan_coo", "spt_status_str",
            "spt_last_error"]
 
@@ -73,6 +74,7 @@ def lib() -> ctypes.CDLL:
     L.spt_remap_for_mode.argtypes = [vp, i32, vp]
     L.spt_mttkrp.argtypes = [vp, i32, vp, i32, i32, vp, ctypes.c_uint32, vp]
     L.spt_cp_als_iter.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    L.spt_cp_gradient.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.spt_tensor_info.argtypes = [vp, vp]
     L.spt_tensor_get_remap.argtypes = [vp, i32, vp]
     L.spt_tensor_get_records.argtypes = [vp, vp, vp, vp]
@@ -180,7 +182,8 @@ def plan_coo(dims, indices, kappa: int = 0, split_cap: Optional[int] = None) -> 
     return {"part": part, "remap": remap, "ptr": ptr, "kappa": k}
 
 
-def _factor_ptrs(t: Tensor, factors: Sequence[Optional[torch.Tensor]], rank: int, skip: int = -1):
+def _factor_ptrs(t: Tensor, factors: Sequence[Optional[torch.Tensor]], rank: int, skip: int = -1,
+                 dtype=torch.float32):
     if len(factors) != t.nmodes:
         raise ValueError("one factor matrix per mode is required")
     arr = (ctypes.c_void_p * t.nmodes)()
@@ -190,9 +193,9 @@ def _factor_ptrs(t: Tensor, factors: Sequence[Optional[torch.Tensor]], rank: int
                 raise ValueError(f"factor {w} is None")
             arr[w] = None
             continue
-        if not (f.is_cuda and f.dtype == torch.float32 and f.is_contiguous()
+        if not (f.is_cuda and f.dtype == dtype and f.is_contiguous()
                 and tuple(f.shape) == (t.dims[w], rank)):
-            raise ValueError(f"factor {w} must be a contiguous CUDA float32 tensor of shape "
+            raise ValueError(f"factor {w} must be a contiguous CUDA {dtype} tensor of shape "
                              f"({t.dims[w]}, {rank})")
         arr[w] = f.data_ptr()
     return arr
@@ -205,25 +208,66 @@ def remap_for_mode(t: Tensor, mode: int, stream=None) -> None:
 def mttkrp(t: Tensor, mode: int, factors: Sequence[Optional[torch.Tensor]], out: torch.Tensor,
            flags: int = 0, stream=None) -> torch.Tensor:
     rank = int(out.shape[1])
-    arr = _factor_ptrs(t, factors, rank, skip=mode)
+    present = [f for f in factors if f is not None]
+    dtype = present[0].dtype if present else torch.float32
+    if dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("factors must be float32 or bfloat16")
+    arr = _factor_ptrs(t, factors, rank, skip=mode, dtype=dtype)
     if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
             and tuple(out.shape) == (t.dims[mode], rank)):
         raise ValueError("out must be a contiguous CUDA float32 tensor of shape (I_mode, R)")
-    _check(lib().spt_mttkrp(t.handle, int(mode), arr, F32, rank, out.data_ptr(), int(flags),
-                            _stream(stream)))
+    _check(lib().spt_mttkrp(t.handle, int(mode), arr, BF16 if dtype == torch.bfloat16 else F32,
+                            rank, out.data_ptr(), int(flags), _stream(stream)))
     return out
 
 
 def cp_als_iter(t: Tensor, factors: Sequence[torch.Tensor], lam: torch.Tensor,
-                want_fit: bool = True, stream=None) -> Optional[float]:
+                want_fit: bool = True, stream=None, bf16_gather: bool = False) -> Optional[float]:
     rank = int(lam.shape[0])
     arr = _factor_ptrs(t, factors, rank)
     if not (lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()):
         raise ValueError("lambda must be a contiguous CUDA float64 tensor of shape (R,)")
     fit = ctypes.c_double(float("nan"))
-    _check(lib().spt_cp_als_iter(t.handle, arr, F32, rank, lam.data_ptr(),
+    _check(lib().spt_cp_als_iter(t.handle, arr, BF16 if bf16_gather else F32, rank, lam.data_ptr(),
                                  ctypes.byref(fit) if want_fit else None, _stream(stream)))
     return fit.value if want_fit else None
+
+
+def cp_gradient(t: Tensor, factors: Sequence[torch.Tensor], grads: Optional[List[torch.Tensor]] = None,
+                stream=None):
+    """loss = 1/2 sum_e (x_e - m_e)^2 over the stored nonzeros and its gradient
+    with respect to every factor.  Returns (loss as a CUDA float64 tensor of
+    shape (1,), grads)."""
+    rank = int(factors[0].shape[1])
+    arr = _factor_ptrs(t, factors, rank)
+    if grads is None:
+        grads = [torch.empty_like(f) for f in factors]
+    garr = _factor_ptrs(t, grads, rank)
+    loss = torch.empty(1, dtype=torch.float64, device=factors[0].device)
+    _check(lib().spt_cp_gradient(t.handle, arr, F32, rank, garr, loss.data_ptr(), _stream(stream)))
+    return loss, grads
+
+
+class CPFitLoss(torch.autograd.Function):
+    """Least-squares CP fit over the stored nonzeros as an autograd function:
+    forward runs the model-at-nonzeros kernel, backward hands back the
+    adjoint (spMTTKRP of the residuals) computed with it."""
+
+    @staticmethod
+    def forward(ctx, t, *factors):
+        fs = [f.detach().contiguous() for f in factors]
+        loss, grads = cp_gradient(t, fs)
+        ctx.save_for_backward(*grads)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, gout):
+        grads = ctx.saved_tensors
+        return (None,) + tuple(g * gout.to(g.dtype) for g in grads)
+
+
+def cp_fit_loss(t: Tensor, factors: Sequence[torch.Tensor]) -> torch.Tensor:
+    return CPFitLoss.apply(t, *factors)
 
 
 def tensor_info(t: Tensor) -> Dict[str, object]:

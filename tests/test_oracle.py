@@ -336,3 +336,74 @@ def test_not_spd_raises_after_one_ridge_retry():
         oracle.als_update(M, [np.zeros((2, 2)), np.zeros((2, 2)), np.eye(2)], 2)
     Y, lam = oracle.als_update(M, G, 0)
     assert np.allclose(np.linalg.norm(Y, axis=0), 1.0)
+
+
+# ---------------------------------------------------------------- BF16 storage
+
+def test_bf16_round_matches_torch_and_special_cases():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([
+        rng.standard_normal(200_000).astype(np.float32) * np.float32(1e3),
+        rng.standard_normal(1000).astype(np.float32) * np.float32(1e-40),   # subnormals
+        np.array([0.0, -0.0, np.inf, -np.inf, 1.0, 65504.0, 3.0e38], np.float32),
+        # exact ties between two BF16 neighbours: even and odd kept parts
+        np.array([0x3F808000, 0x3F818000, 0xBF808000, 0x7F7F8000], np.uint32).view(np.float32),
+    ])
+    ours = oracle.bf16_round(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(ours.view(np.uint32), ref.view(np.uint32))
+    # ties go to the even neighbour
+    t = np.array([0x3F808000, 0x3F818000], np.uint32).view(np.float32)
+    assert oracle.bf16_round(t).view(np.uint32).tolist() == [0x3F800000, 0x3F820000]
+    n = oracle.bf16_round(np.array([np.nan], np.float32))
+    assert np.isnan(n[0])
+    # relative rounding error is at most half an ulp: 2^-8 (8 significand bits)
+    y = rng.uniform(0.5, 2.0, 10_000).astype(np.float32)
+    assert np.max(np.abs(oracle.bf16_round(y) - y) / y) <= 2.0 ** -8
+
+
+# ---------------------------------------------------------------- gradient fit
+
+def test_cp_gradient_against_central_differences():
+    dims = (6, 5, 4)
+    idx, val = synth.random_coo(dims, 40, seed=41)
+    Y = [y.astype(np.float64) for y in synth.random_factors(dims, 3, seed=42)]
+    loss, grads = oracle.cp_loss_grad(dims, idx, val, Y)
+    h = 1e-6
+    rng = np.random.default_rng(1)
+    for d in range(3):
+        for _ in range(6):
+            i, r = int(rng.integers(dims[d])), int(rng.integers(3))
+            Yp = [y.copy() for y in Y]
+            Ym = [y.copy() for y in Y]
+            Yp[d][i, r] += h
+            Ym[d][i, r] -= h
+            fd = (oracle.cp_loss_grad(dims, idx, val, Yp)[0] -
+                  oracle.cp_loss_grad(dims, idx, val, Ym)[0]) / (2 * h)
+            assert abs(fd - grads[d][i, r]) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_cp_gradient_matches_dense_autograd_and_planted_residuals():
+    torch = pytest.importorskip("torch")
+    dims = (5, 4, 6, 3)
+    idx, _ = synth.random_coo(dims, 60, seed=43)
+    lin = np.ravel_multi_index(tuple(idx), dims)
+    _, first = np.unique(lin, return_index=True)
+    idx = idx[:, np.sort(first)]                      # distinct coordinates
+    Y = [y.astype(np.float64) for y in synth.random_factors(dims, 2, seed=44)]
+    # values = the planted model (dense einsum, independent of the oracle) + noise
+    Xhat = np.einsum("ar,br,cr,dr->abcd", *Y)
+    noise = 0.01 * np.random.default_rng(2).standard_normal(idx.shape[1])
+    val = Xhat[tuple(idx)] + noise
+    loss, grads = oracle.cp_loss_grad(dims, idx, val, Y)
+    assert np.allclose(oracle.model_at(idx, Y) - val, -noise, atol=1e-12)
+    assert abs(loss - 0.5 * np.dot(noise, noise)) <= 1e-12
+    # dense masked least squares differentiated by torch (float64)
+    tY = [torch.tensor(y, requires_grad=True) for y in Y]
+    T = torch.einsum("ar,br,cr,dr->abcd", *tY)
+    L = 0.5 * ((T[tuple(torch.tensor(i) for i in idx)] - torch.tensor(val)) ** 2).sum()
+    L.backward()
+    assert abs(L.item() - loss) <= 1e-12
+    for g, t in zip(grads, tY):
+        assert np.allclose(g, t.grad.numpy(), rtol=1e-10, atol=1e-12)
