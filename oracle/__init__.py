@@ -92,6 +92,34 @@ def mttkrp(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
     return out
 
 
+def mttkrp_rows(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
+                factors: Sequence[np.ndarray], mode: int, rows: Sequence[int]) -> np.ndarray:
+    """Eq. (1) restricted to the listed output rows: FP64 [len(rows), R].
+
+    For full-size tensors, where only sampled rows are checked.  The nonzeros
+    of the listed rows are found by a scan over i_mode; each contributes
+    val_e times the product of the other modes' factor rows, summed per row
+    column by column (``np.bincount`` with weights, in FP64)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    uniq = np.unique(rows)
+    R = int(factors[0].shape[1])
+    acc = np.zeros((uniq.size, R), dtype=np.float64)
+    col = np.asarray(idx[mode])
+    pos = np.searchsorted(uniq, col)
+    hit = np.flatnonzero(uniq[np.minimum(pos, uniq.size - 1)] == col)
+    step = 1 << 20
+    for a in range(0, hit.size, step):
+        e = hit[a:a + step]
+        term = np.repeat(np.asarray(val[e], dtype=np.float64)[:, None], R, axis=1)
+        for w in range(len(dims)):
+            if w != mode:
+                term *= np.asarray(factors[w], dtype=np.float64)[idx[w, e]]
+        loc = pos[e]
+        for r in range(R):
+            acc[:, r] += np.bincount(loc, weights=term[:, r], minlength=uniq.size)
+    return acc[np.searchsorted(uniq, rows)]
+
+
 # ---------------------------------------------------------------------------
 # Algorithm 1 and the remap ids
 # ---------------------------------------------------------------------------

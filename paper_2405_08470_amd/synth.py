@@ -119,10 +119,12 @@ def zipf_ranks(seed: int, sid: int, n: int, size: int, s: float) -> np.ndarray:
 
 
 # Stream ids: mode d indices -> d; factor w -> 16 + w; values -> 32;
-# noise -> 33; permutations of mode d -> 48 + d; top-up draws -> 64 + round.
+# noise -> 33; starting-point perturbation of factor w -> 40 + w;
+# permutations of mode d -> 48 + d; top-up draws -> 64 + round.
 SID_FACTOR = 16
 SID_VALUES = 32
 SID_NOISE = 33
+SID_START = 40
 SID_PERM = 48
 SID_TOPUP = 64
 
@@ -137,9 +139,10 @@ class TensorSpec:
     rank: int
     dist: str = "uniform_distinct"   # or "zipf"
     zipf_s: float = 1.1
-    values: str = "uniform"          # or "lognormal"
+    values: str = "uniform"          # "lognormal", or "planted" (see planted_parts)
     seed: int = 1
     als_iters: int = 5
+    noise_sd: float = 0.0            # planted values: standard deviation of the noise
 
     @property
     def nmodes(self) -> int:
@@ -158,6 +161,11 @@ CONFIGS = {
                   "zipf", 1.2, "lognormal", seed=3, als_iters=10),
     4: TensorSpec("zipf4_1e8", (50_000, 50_000, 20_000, 1_000), 100_000_000, 64,
                   "zipf", 1.1, "uniform", seed=4, als_iters=10),
+    # Observed entries of a planted rank-16 model plus N(0, 0.01^2) noise:
+    # the gradient-fit workload.
+    5: TensorSpec("planted4_5e7", (20_000, 20_000, 10_000, 500), 50_000_000, 16,
+                  "uniform_distinct", values="planted", seed=5, als_iters=0,
+                  noise_sd=0.01),
 }
 
 
@@ -169,6 +177,25 @@ def scaled(spec: TensorSpec, nnz: int, dims: Optional[Sequence[int]] = None,
         rank=spec.rank if rank is None else int(rank),
         seed=spec.seed if seed is None else int(seed),
         name=f"{spec.name}@{nnz}")
+
+
+def _first_copies(keys: np.ndarray) -> np.ndarray:
+    """Boolean mask keeping the first occurrence of every key (draw order)."""
+    srt = np.sort(keys)
+    rep = np.unique(srt[1:][srt[1:] == srt[:-1]])
+    keep = np.ones(keys.size, dtype=bool)
+    if rep.size:
+        pos = np.searchsorted(rep, keys)
+        hit = np.flatnonzero(rep[np.minimum(pos, rep.size - 1)] == keys)
+        # among the positions holding a repeated key, keep the first of each
+        order = np.lexsort((hit, keys[hit]))
+        h = hit[order]
+        k = keys[h]
+        later = np.ones(h.size, dtype=bool)
+        later[0] = False
+        later[1:] = k[1:] == k[:-1]
+        keep[h[later]] = False
+    return keep
 
 
 def _uniform_distinct(spec: TensorSpec) -> np.ndarray:
@@ -195,9 +222,7 @@ def _uniform_distinct(spec: TensorSpec) -> np.ndarray:
         for d, I in enumerate(dims):
             lin = lin * int(I) + cols[d]
         allk = np.concatenate([keys, lin])
-        _, first = np.unique(allk, return_index=True)
-        first.sort()
-        keys = allk[first]
+        keys = allk[_first_copies(allk)]
         if keys.size >= spec.nnz:
             keys = keys[: spec.nnz]
             break
@@ -232,9 +257,38 @@ def make_coo(spec: TensorSpec) -> Tuple[Tuple[int, ...], np.ndarray, np.ndarray]
         val = uniform01(spec.seed, SID_VALUES, spec.nnz).astype(np.float32)
     elif spec.values == "lognormal":
         val = np.exp(normal(spec.seed, SID_VALUES, spec.nnz)).astype(np.float32)
+    elif spec.values == "planted":
+        raise ValueError("planted values are the model at the nonzeros plus noise: "
+                         "draw the parts with planted_parts() and evaluate the model there")
     else:
         raise ValueError(spec.values)
     return tuple(int(i) for i in spec.dims), idx, val
+
+
+def planted_parts(spec: TensorSpec):
+    """Draws of a planted workload: (dims, indices int32 [N, nnz], planted
+    factors P_w (FP32, I_w x R, entries N(0,1) * R^(-1/(2N)) so that the model
+    at a nonzero has unit variance), noise (FP64 [nnz], N(0, noise_sd^2))).
+    The observed value is x_e = sum_r prod_w P_w(i_w(e), r) + noise_e; that
+    sum is left to the caller."""
+    if spec.values != "planted":
+        raise ValueError("not a planted workload")
+    dims = tuple(int(i) for i in spec.dims)
+    if spec.dist == "uniform_distinct":
+        idx = _uniform_distinct(spec)
+    else:
+        idx = _zipf(spec)
+    scale = float(spec.rank) ** (-1.0 / (2 * spec.nmodes))
+    P = [(normal(spec.seed, SID_FACTOR + w, I * spec.rank) * scale).astype(np.float32)
+         .reshape(I, spec.rank) for w, I in enumerate(dims)]
+    noise = normal(spec.seed, SID_NOISE, spec.nnz) * spec.noise_sd
+    return dims, idx, P, noise
+
+
+def planted_start(spec: TensorSpec, P: Sequence[np.ndarray], sd: float = 0.1) -> List[np.ndarray]:
+    """Starting point of a fit: the planted factors plus N(0, sd^2) entries."""
+    return [(P[w].astype(np.float64) + sd * normal(spec.seed, SID_START + w, P[w].size)
+             .reshape(P[w].shape)).astype(np.float32) for w in range(len(P))]
 
 
 def make_factors(spec: TensorSpec, rank: Optional[int] = None) -> List[np.ndarray]:

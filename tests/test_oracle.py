@@ -125,6 +125,20 @@ def test_mttkrp_empty_rows_are_zero_and_bad_index_rejected():
     assert np.all(oracle.mttkrp(dims, idx[:, :0], val[:0], Y, 2) == 0)
 
 
+@pytest.mark.parametrize("dims", [(40, 9), (30, 20, 10), (12, 9, 7, 5), (8, 7, 6, 5, 4)])
+def test_mttkrp_rows_equals_the_full_loop_on_sampled_rows(dims):
+    # the row-restricted form used on full-size tensors, against the pinned loop
+    idx, val = synth.random_coo(dims, 3000, seed=len(dims), dist="zipf")
+    Y = synth.random_factors(dims, 6, seed=11)
+    for d in range(len(dims)):
+        M = oracle.mttkrp(dims, idx, val, Y, d)
+        deg = np.bincount(idx[d], minlength=dims[d])
+        rows = [int(np.argmax(deg)), int(np.argmin(deg)), 0, dims[d] - 1, int(np.argmax(deg))]
+        got = oracle.mttkrp_rows(dims, idx, val, Y, d, rows)
+        assert got.shape == (len(rows), 6)
+        assert np.allclose(got, M[rows], rtol=1e-12, atol=1e-12)
+
+
 # ---------------------------------------------------------------- Alg. 1
 
 def test_partition_worked_example():
