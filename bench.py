@@ -13,7 +13,16 @@ Phases (inputs resident in HBM before any timed region):
      factor): K timed steps -> `ms_per_step`;
   C  the same spMTTKRP on one mode-ordered copy per mode (no remapping) ->
      the remapping share of A (the paper's breakdown experiment, Sec. 5.2);
-  the FP64 oracle on a bounded sample of the same tensor on the host cores.
+  D  A's passes with BF16 factor storage and gathers (FP32 accumulation);
+  E  the 4-mode 50000 x 50000 x 20000 x 1000 Zipf(1.1) tensor, 1e8 nonzeros,
+     rank 64: all-mode passes with FP32 and with BF16 factors, and the
+     relative difference of their outputs per mode;
+  F  the 4-mode 20000 x 20000 x 10000 x 500 tensor of 5e7 distinct uniform
+     entries of a planted rank-16 model plus N(0, 0.01^2) noise: the gradient
+     of the least-squares fit over the nonzeros (forward model at the
+     nonzeros + adjoint spMTTKRP of the residuals), timed beside the plain
+     FP32 all-mode spMTTKRP of the same tensor;
+  the FP64 oracle on a bounded sample of the A tensor on the host cores.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -83,6 +92,122 @@ def cpu_baseline(dims, idx, val, factors, budget_s):
     return ts * 1e3 * nnz / S, S, ts
 
 
+def timed_passes(torch, S, t, K, W, fn):
+    """W untimed, then K timed calls of fn(); wall ms per call and the
+    library's per-mode kernel-event totals over the timed calls."""
+    for _ in range(W):
+        fn()
+    torch.cuda.synchronize()
+    S.timing_control(t, True, want=False)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(K):
+        fn()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) * 1e3 / K
+    tm = S.timing_control(t, False)
+    return wall, tm
+
+
+def per_call(tm, key, N):
+    return [tm[key][d] / max(1, tm["calls"][d]) for d in range(N)]
+
+
+def phase_bf16_wide(torch, S, synth, K, W):
+    """Phase E: FP32 against BF16 factors on the 4-mode rank-64 workload."""
+    spec = synth.CONFIGS[4]
+    t0 = time.perf_counter()
+    dims, idx, val = synth.make_coo(spec)
+    Y = synth.make_factors(spec)
+    log(f"phase E: generated {spec.name} in {time.perf_counter() - t0:.1f}s")
+    N, R = len(dims), spec.rank
+    t = S.tensor_load_coo(dims, idx, val, prep="device")
+    del idx, val
+    info = S.tensor_info(t)
+    f32 = [torch.from_numpy(y).cuda() for y in Y]
+    fbf = [f.to(torch.bfloat16) for f in f32]
+    outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
+    res = {}
+    keep = []
+    for name, fac in (("fp32", f32), ("bf16", fbf)):
+        def run(fac=fac):
+            for d in range(N):
+                S.mttkrp(t, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
+        wall, tm = timed_passes(torch, S, t, K, W, run)
+        ec = per_call(tm, "ec_ms", N)
+        res[name] = {"ms_per_pass": round(wall, 4), "ec_remap_kernel_ms": [round(x, 4) for x in ec]}
+        keep.append([o.clone() for o in outs])
+        log(f"phase E {name}: {wall:.3f} ms per all-mode pass; kernels {['%.3f' % x for x in ec]} ms")
+    err = [float(torch.linalg.vector_norm(keep[1][d] - keep[0][d]) / torch.linalg.vector_norm(keep[0][d]))
+           for d in range(N)]
+    log(f"phase E: BF16 vs FP32 factors, rel diff per mode {['%.2e' % e for e in err]}")
+    t.free()
+    return {"workload": f"{spec.name}: 4-mode {'x'.join(map(str, dims))}, {spec.nnz} nonzeros, "
+                        f"Zipf({spec.zipf_s}) shuffled, rank {R}",
+            "kappa": info["kappa"], **res,
+            "bf16_rel_diff_vs_fp32": [float("%.3g" % e) for e in err],
+            "speedup_bf16": round(res["fp32"]["ms_per_pass"] / res["bf16"]["ms_per_pass"], 3)}
+
+
+def planted_values(idx, P, noise):
+    """x_e = sum_r prod_w P_w(i_w(e), r) + noise_e (the planted workload's
+    observed values), evaluated here in chunks, FP64 then rounded to FP32."""
+    nnz = idx.shape[1]
+    out = np.empty(nnz, dtype=np.float32)
+    step = 1 << 22
+    for a in range(0, nnz, step):
+        b = min(nnz, a + step)
+        p = np.ones((b - a, P[0].shape[1]), dtype=np.float64)
+        for w in range(len(P)):
+            p *= P[w][idx[w, a:b]]
+        out[a:b] = (p.sum(axis=1) + noise[a:b]).astype(np.float32)
+    return out
+
+
+def phase_gradient(torch, S, synth, K, W):
+    """Phase F: gradient of the CP fit over the nonzeros vs plain spMTTKRP."""
+    spec = synth.CONFIGS[5]
+    t0 = time.perf_counter()
+    dims, idx, P, noise = synth.planted_parts(spec)
+    val = planted_values(idx, P, noise)
+    start = synth.planted_start(spec, P)
+    log(f"phase F: generated {spec.name} in {time.perf_counter() - t0:.1f}s")
+    N, R = len(dims), spec.rank
+    t = S.tensor_load_coo(dims, idx, val, prep="device")
+    del idx, val
+    info = S.tensor_info(t)
+    fac = [torch.from_numpy(y).cuda() for y in start]
+    grads = [torch.empty_like(f) for f in fac]
+    outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
+
+    def grad():
+        S.cp_gradient(t, fac, grads)
+
+    def plain():
+        for d in range(N):
+            S.mttkrp(t, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
+
+    wall_g, tm_g = timed_passes(torch, S, t, K, W, grad)
+    wall_p, tm_p = timed_passes(torch, S, t, K, W, plain)
+    loss_start = float(S.cp_gradient(t, fac, grads)[0].item())
+    pf = [torch.from_numpy(p).cuda() for p in P]
+    loss_planted = float(S.cp_gradient(t, pf, [torch.empty_like(p) for p in pf])[0].item())
+    noise_half_ss = 0.5 * float(np.dot(noise, noise))
+    t.free()
+    log(f"phase F: gradient {wall_g:.3f} ms (forward + {N} adjoint modes); plain FP32 all-mode "
+        f"spMTTKRP {wall_p:.3f} ms; loss at start {loss_start:.4g}, at the planted factors "
+        f"{loss_planted:.6g} (half the noise sum of squares {noise_half_ss:.6g})")
+    return {"workload": f"{spec.name}: 4-mode {'x'.join(map(str, dims))}, {spec.nnz} distinct uniform "
+                        f"nonzeros of a planted rank-{R} model + N(0, {spec.noise_sd}^2) noise",
+            "kappa": info["kappa"],
+            "gradient_ms": round(wall_g, 4),
+            "adjoint_ec_kernel_ms": [round(x, 4) for x in per_call(tm_g, "ec_ms", N)],
+            "plain_fp32_all_mode_ms": round(wall_p, 4),
+            "plain_ec_kernel_ms": [round(x, 4) for x in per_call(tm_p, "ec_ms", N)],
+            "loss_at_start": loss_start, "loss_at_planted": loss_planted,
+            "half_noise_sum_sq": noise_half_ss}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +219,8 @@ def main() -> int:
     ap.add_argument("--no-ec-only", action="store_true", help="skip phase C")
     ap.add_argument("--no-als", action="store_true", help="skip phase B")
     ap.add_argument("--no-bf16", action="store_true", help="skip phase D")
+    ap.add_argument("--no-wide", action="store_true", help="skip phases E and F")
+    ap.add_argument("--no-host-prep", action="store_true", help="skip the host-planner load timing")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     args = ap.parse_args()
 
@@ -119,10 +246,16 @@ def main() -> int:
     log(f"generated {spec.name}: dims {dims} nnz {spec.nnz} R {R} in {time.perf_counter() - t0:.1f}s")
     N = len(dims)
 
-    t = S.tensor_load_coo(dims, idx, val, kappa=args.kappa)
+    prep_host = None
+    if not args.no_host_prep:
+        th = S.tensor_load_coo(dims, idx, val, kappa=args.kappa)
+        prep_host = S.tensor_info(th)["prep_seconds"]
+        th.free()
+        log(f"host planner load: {prep_host:.2f}s")
+    t = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, prep="device")
     info = S.tensor_info(t)
-    log(f"loaded: kappa {info['kappa']} record {info['record_bytes']} B prep {info['prep_seconds']:.1f}s "
-        f"max partition {info['max_load']} split rows {info['split_rows']}")
+    log(f"loaded (device planner): kappa {info['kappa']} record {info['record_bytes']} B prep "
+        f"{info['prep_seconds']:.2f}s max partition {info['max_load']} split rows {info['split_rows']}")
     fac = [torch.from_numpy(np.ascontiguousarray(y)).cuda() for y in Y0]
     outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
 
@@ -146,6 +279,13 @@ def main() -> int:
     fix_ms = [tm_a["fixup_ms"][d] / max(1, tm_a["calls"][d]) for d in range(N)]
     log(f"phase A: {wall_a:.3f} ms per all-mode pass; EC+remap kernel per mode {['%.3f' % x for x in ec_ms]} ms, "
         f"fixup {['%.3f' % x for x in fix_ms]} ms")
+
+    # the remap alone (Alg. 3 as a separate scatter kernel), N hops per pass
+    def remap_pass():
+        for d in range(N):
+            S.remap_for_mode(t, (d + 1) % N)
+    wall_r, _ = timed_passes(torch, S, t, K, W, remap_pass)
+    log(f"remap alone: {wall_r:.3f} ms per pass of {N} scatters")
 
     rec = info["record_bytes"]
     bytes_a = [algorithmic_bytes(dims, spec.nnz, R, rec, d, True) for d in range(N)]
@@ -208,7 +348,7 @@ def main() -> int:
     ec_only = None
     ec_only_kernel = None
     if not args.no_ec_only:
-        tc = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, copies=1)
+        tc = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, copies=1, prep="device")
         for _ in range(W):
             all_modes(tc, False)
         torch.cuda.synchronize()
@@ -234,6 +374,12 @@ def main() -> int:
                "sample": f"first {S_n} of {spec.nnz} nonzeros, all {N} modes, FP64 COO loop "
                          f"({ts:.1f} s), scaled linearly to the whole tensor"}
         log(f"cpu oracle: {ms_full:.0f} ms per all-mode pass (extrapolated from {S_n} nonzeros)")
+
+    wide_bf16 = wide_grad = None
+    if not args.no_wide:
+        del idx, val
+        wide_bf16 = phase_bf16_wide(torch, S, synth, K, W)
+        wide_grad = phase_gradient(torch, S, synth, K, W)
 
     kernel = f"ec_kernel<{N},{R},{rec // 4}>"
     line = {
@@ -269,10 +415,14 @@ def main() -> int:
             "ec_only_ms_per_pass": round(ec_only, 4) if ec_only is not None else None,
             "ec_only_kernel_ms": [round(x, 4) for x in ec_only_kernel] if ec_only_kernel else None,
             "remap_share": round(1 - ec_only / wall_a, 4) if ec_only is not None else None,
+            "remap_alone_ms_per_pass": round(wall_r, 4),
             "canonical_record_GBps": round(sum(bytes_canon) / (sum(ec_ms) * 1e-3) / 1e9, 1),
             "fit": fit,
             "bf16_gather": bf16,
-            "prep_seconds": round(info["prep_seconds"], 2),
+            "bf16_rank64_4mode": wide_bf16,
+            "gradient_rank16_4mode": wide_grad,
+            "prep_seconds_device_planner": round(info["prep_seconds"], 3),
+            "prep_seconds_host_planner": round(prep_host, 3) if prep_host is not None else None,
             "copy_GBps": round(copy_gbps, 1),
             "split_rows": info["split_rows"],
             "max_partition": info["max_load"],

@@ -57,7 +57,12 @@ typedef struct spt_opts {
     int64_t split_cap;  /* rows with more nonzeros are cut into pieces of at
                            most this many (extension to Alg. 1, see
                            spt_plan_coo); 0 = ceil(nnz / kappa); -1 = never  */
-    int32_t reserved[4];/* must be zero                                      */
+    int32_t prep;       /* where the per-nonzero preprocessing runs: 0 = host
+                           threads, 1 = device kernels (row sorts, stream
+                           orders, remap ids, packing; Alg. 1's assignment
+                           stays on the host).  Same tables and streams
+                           either way; ||X||^2 up to FP64 summation order  */
+    int32_t reserved[3];/* must be zero                                      */
 } spt_opts;
 
 /* Summary of a loaded tensor (spt_tensor_info). */
@@ -71,7 +76,7 @@ typedef struct spt_info {
     int64_t max_load[8];     /* largest partition of each mode (nonzeros)    */
     int64_t split_rows[8];   /* rows cut into pieces, per mode               */
     double norm_sq;          /* ||X||_F^2 with repeated coordinates summed   */
-    double prep_seconds;     /* host preprocessing time of the load          */
+    double prep_seconds;     /* wall time of the load (preprocessing + upload) */
     int64_t device_bytes;    /* device memory held by the handle             */
 } spt_info;
 

@@ -82,8 +82,21 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
     }
 }
 
-// In-place Cholesky of the R x R matrix in A (lower triangle); returns
-// false if a pivot is not positive.
+// V = Hadamard product of the other modes' Grams, plus `ridge` on the diagonal.
+template <int R>
+__device__ void build_normal(double (*A)[R + 1], const double* __restrict__ grams, int nmodes,
+                             int mode, double ridge) {
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+        const int r = e / R, c = e % R;
+        double v = 1.0;
+        for (int w = 0; w < nmodes; ++w)
+            if (w != mode) v *= grams[(int64_t)w * R * R + e];
+        A[r][c] = v + (r == c ? ridge : 0.0);
+    }
+}
+
+// Right-looking Cholesky of A in place (lower triangle), all threads of the
+// block; returns false if a pivot is not positive.
 template <int R>
 __device__ bool cholesky(double (*A)[R + 1]) {
     __shared__ int ok;
@@ -93,7 +106,6 @@ __device__ bool cholesky(double (*A)[R + 1]) {
     for (int j = 0; j < R; ++j) {
         if (tid == 0) {
             double d = A[j][j];
-            for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
             if (!(d > 0.0)) {
                 ok = 0;
                 d = 1.0;
@@ -101,14 +113,37 @@ __device__ bool cholesky(double (*A)[R + 1]) {
             A[j][j] = sqrt(d);
         }
         __syncthreads();
-        for (int i = j + 1 + tid; i < R; i += blockDim.x) {
-            double x = A[i][j];
-            for (int k = 0; k < j; ++k) x -= A[i][k] * A[j][k];
-            A[i][j] = x / A[j][j];
+        for (int i = j + 1 + tid; i < R; i += blockDim.x) A[i][j] /= A[j][j];
+        __syncthreads();
+        const int m = R - j - 1;
+        for (int e = tid; e < m * m; e += blockDim.x) {
+            const int i = j + 1 + e / m, k = j + 1 + e % m;
+            if (k <= i) A[i][k] -= A[i][j] * A[k][j];
         }
         __syncthreads();
     }
     return ok != 0;
+}
+
+// In-place Gauss-Jordan inverse of the SPD matrix in A (no pivoting: the
+// pivots are the Schur complements, positive for an SPD matrix).
+template <int R>
+__device__ void gauss_jordan_inverse(double (*A)[R + 1]) {
+    __shared__ double colk[R];
+    __shared__ double piv;
+    const int tid = threadIdx.x;
+    for (int k = 0; k < R; ++k) {
+        if (tid < R) colk[tid] = A[tid][k];
+        if (tid == 0) piv = A[k][k];
+        __syncthreads();
+        for (int c = tid; c < R; c += blockDim.x) A[k][c] = (c == k ? 1.0 : A[k][c]) / piv;
+        __syncthreads();
+        for (int e = tid; e < R * R; e += blockDim.x) {
+            const int i = e / R, c = e % R;
+            if (i != k) A[i][c] = (c == k ? 0.0 : A[i][c]) - colk[i] * A[k][c];
+        }
+        __syncthreads();
+    }
 }
 
 template <int R>
@@ -117,56 +152,38 @@ __global__ __launch_bounds__(256) void normal_inverse_kernel(const double* __res
                                                               double* __restrict__ Vinv,
                                                               int32_t* __restrict__ status) {
     __shared__ double A[R][R + 1];
-    __shared__ double B[R][R + 1];
+    __shared__ double ridge;
     const int tid = threadIdx.x;
-    // V = Hadamard product of the other modes' Grams
-    for (int e = tid; e < R * R; e += blockDim.x) {
-        const int r = e / R, c = e % R;
-        double v = 1.0;
-        for (int w = 0; w < nmodes; ++w)
-            if (w != mode) v *= grams[(int64_t)w * R * R + e];
-        A[r][c] = v;
-        B[r][c] = v;
-    }
+    build_normal<R>(A, grams, nmodes, mode, 0.0);
     __syncthreads();
     bool ok = cholesky<R>(A);
+    double rg = 0.0;
     if (!ok) {
-        __shared__ double ridge;
+        // one retry with 1e-12 tr(V) / R on the diagonal
+        __syncthreads();
+        build_normal<R>(A, grams, nmodes, mode, 0.0);
+        __syncthreads();
         if (tid == 0) {
             double tr = 0.0;
-            for (int j = 0; j < R; ++j) tr += B[j][j];
+            for (int j = 0; j < R; ++j) tr += A[j][j];
             ridge = 1e-12 * tr / R;
         }
         __syncthreads();
-        for (int e = tid; e < R * R; e += blockDim.x) {
-            const int r = e / R, c = e % R;
-            A[r][c] = B[r][c] + (r == c ? ridge : 0.0);
-        }
+        rg = ridge;
+        build_normal<R>(A, grams, nmodes, mode, rg);
         __syncthreads();
         ok = cholesky<R>(A);
         if (!ok && tid == 0) status[0] |= 1;
     }
     __syncthreads();
-    // Linv (lower): column c solves L x = e_c by forward substitution
-    for (int c = tid; c < R; c += blockDim.x) {
-        for (int i = 0; i < R; ++i) {
-            if (i < c) {
-                B[i][c] = 0.0;
-                continue;
-            }
-            double x = (i == c) ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) x -= A[i][k] * B[k][c];
-            B[i][c] = x / A[i][i];
-        }
+    if (!ok) {
+        for (int e = tid; e < R * R; e += blockDim.x) Vinv[e] = 0.0;
+        return;
     }
+    build_normal<R>(A, grams, nmodes, mode, rg);
     __syncthreads();
-    // V^-1 = Linv^T Linv
-    for (int e = tid; e < R * R; e += blockDim.x) {
-        const int r = e / R, c = e % R;
-        double s = 0.0;
-        for (int k = (r > c ? r : c); k < R; ++k) s += B[k][r] * B[k][c];
-        Vinv[e] = ok ? s : 0.0;
-    }
+    gauss_jordan_inverse<R>(A);
+    for (int e = tid; e < R * R; e += blockDim.x) Vinv[e] = A[e / R][e % R];
 }
 
 template <int R>
@@ -232,6 +249,132 @@ __global__ __launch_bounds__(256) void solve_rows_kernel(const float* __restrict
         double s = 0.0;
         for (int i = 0; i < RB; ++i) s += ired[i][tid];
         ipart[(int64_t)blockIdx.x * R + tid] = s;
+    }
+}
+
+// Y = M V^-1 on the FP64 matrix cores (v_mfma_f64_16x16x4f64), for R a
+// multiple of 16.  Each wave takes 16-row tiles.  Operand layout of the
+// instruction (wave64): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// of a 16x4 by 4x16 step and holds D[4 (l / 16) + v][l % 16], v = 0..3, of
+// the 16x16 result.  The contraction index k of step s for lane group
+// q = l / 16 is k = q R/4 + s, so a lane's A values are R/4 consecutive
+// columns of its row of M (vector loads) and its B values are the matching
+// rows of V^-1 (held in registers for the whole kernel).  The rounded FP32
+// result feeds the Gram of the unnormalised factor with no data movement:
+// for fixed v, the four rows 4q + v of a tile are the k index of one more
+// step, A = column tile c0 and B = column tile c1 of those rows.  <M, Y>
+// per column (for the fit) is summed in FP64 per lane.
+template <int R>
+__global__ __launch_bounds__(256) void solve_rows_mfma_kernel(const float* __restrict__ M,
+                                                               const double* __restrict__ Vinv,
+                                                               int64_t rows, float* __restrict__ Y,
+                                                               double* __restrict__ gpart,
+                                                               double* __restrict__ ipart) {
+    static_assert(R % 16 == 0, "rank");
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    constexpr int CT = R / 16;             // column tiles
+    constexpr int KS = R / 4;              // steps of the solve
+    constexpr int NP = CT * (CT + 1) / 2;  // Gram tiles c0 <= c1
+    constexpr int E = R * R;
+    __shared__ double gsh[E];
+    __shared__ double ish[4][4][R];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rl = lane & 15, q = lane >> 4;
+
+    double bv[CT][KS];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) bv[ct][s] = Vinv[(q * KS + s) * R + 16 * ct + rl];
+    v4d gacc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) gacc[p] = v4d{0.0, 0.0, 0.0, 0.0};
+    double iacc[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) iacc[ct] = 0.0;
+
+    const int64_t tiles = (rows + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t r0 = tile * 16;
+        float av[KS];
+        const int64_t ra = r0 + rl;
+        if (ra < rows) {
+            const float4* src = reinterpret_cast<const float4*>(M + ra * R + q * KS);
+#pragma unroll
+            for (int j = 0; j < KS / 4; ++j) {
+                const float4 x = src[j];
+                av[4 * j] = x.x;
+                av[4 * j + 1] = x.y;
+                av[4 * j + 2] = x.z;
+                av[4 * j + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < KS; ++j) av[j] = 0.0f;
+        }
+        v4d acc[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[s], bv[ct][s], acc[ct], 0, 0, 0);
+        double yd[CT][4];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = r0 + 4 * q + v;
+                const int col = 16 * ct + rl;
+                double y = 0.0;
+                if (row < rows) {
+                    const float yf = (float)acc[ct][v];
+                    Y[row * R + col] = yf;
+                    y = (double)yf;
+                    iacc[ct] += (double)M[row * R + col] * y;
+                }
+                yd[ct][v] = y;
+            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int p = 0;
+#pragma unroll
+            for (int c0 = 0; c0 < CT; ++c0)
+#pragma unroll
+                for (int c1 = c0; c1 < CT; ++c1, ++p)
+                    gacc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(yd[c0][v], yd[c1][v], gacc[p], 0, 0, 0);
+        }
+    }
+    // the waves' Gram tiles (and their transposes) summed in LDS in wave
+    // order; every entry belongs to one lane of a wave
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w) {
+            int p = 0;
+#pragma unroll
+            for (int c0 = 0; c0 < CT; ++c0)
+#pragma unroll
+                for (int c1 = c0; c1 < CT; ++c1, ++p)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * c0 + 4 * q + v, j = 16 * c1 + rl;
+                        const double x = gacc[p][v];
+                        gsh[i * R + j] = w == 0 ? x : gsh[i * R + j] + x;
+                        if (c1 != c0) gsh[j * R + i] = w == 0 ? x : gsh[j * R + i] + x;
+                    }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) ish[wv][q][16 * ct + rl] = iacc[ct];
+    __syncthreads();
+    for (int e = threadIdx.x; e < E; e += 256) gpart[(int64_t)blockIdx.x * E + e] = gsh[e];
+    if (threadIdx.x < R) {
+        const int c = threadIdx.x;
+        double t = 0.0;
+        for (int w = 0; w < 4; ++w)
+            for (int g = 0; g < 4; ++g) t += ish[w][g][c];
+        ipart[(int64_t)blockIdx.x * R + c] = t;
     }
 }
 
@@ -311,6 +454,8 @@ void by_rank(int rank, dim3 grid, dim3 block, hipStream_t s, Args... args) {
 template <int R> struct GramP { static constexpr auto fn = gram_partial_kernel<R>; };
 template <int R> struct NormInv { static constexpr auto fn = normal_inverse_kernel<R>; };
 template <int R> struct Solve { static constexpr auto fn = solve_rows_kernel<R>; };
+template <int R> struct SolveMfma { static constexpr auto fn = solve_rows_mfma_kernel<R>; };
+template <> struct SolveMfma<8> { static constexpr auto fn = solve_rows_kernel<8>; };
 template <int R> struct Finish { static constexpr auto fn = als_finish_kernel<R>; };
 template <int R> struct Scale { static constexpr auto fn = scale_cols_kernel<R>; };
 
@@ -340,7 +485,7 @@ int solve_blocks(int64_t rows) {
 
 void launch_solve_rows(int rank, const float* M, const double* Vinv, int64_t rows, float* Y,
                        double* gpart, double* ipart, hipStream_t s) {
-    by_rank<Solve>(rank, dim3(solve_blocks(rows)), dim3(256), s, M, Vinv, rows, Y, gpart, ipart);
+    by_rank<SolveMfma>(rank, dim3(solve_blocks(rows)), dim3(256), s, M, Vinv, rows, Y, gpart, ipart);
 }
 
 void launch_als_finish(int rank, int nmodes, int mode, const double* Gun, const double* Isum,

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "device_plan.hpp"
 #include "plan.hpp"
 
 using spt::Plan;
@@ -136,8 +137,10 @@ void release(spt_tensor_s* t) {
 spt_status get_opts(const spt_opts* o, PlanOptions* po, int* copies) {
     *copies = 0;
     if (!o) return SPT_OK;
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 3; ++k)
         if (o->reserved[k] != 0) return fail(SPT_ERR_INVALID_ARG, "opts.reserved must be zero");
+    if (o->prep != 0 && o->prep != 1) return fail(SPT_ERR_INVALID_ARG, "opts.prep must be 0 or 1");
+    po->prep = o->prep;
     if (o->kappa < 0) return fail(SPT_ERR_INVALID_ARG, "opts.kappa must be >= 0");
     if (o->copies != 0 && o->copies != 1) return fail(SPT_ERR_INVALID_ARG, "opts.copies must be 0 or 1");
     if (o->split_cap < -1) return fail(SPT_ERR_INVALID_ARG, "opts.split_cap must be >= -1");
@@ -346,6 +349,91 @@ spt_status spt_plan_coo(int32_t nmodes, const int64_t* dims, int64_t nnz, const 
     return SPT_OK;
 }
 
+namespace {
+
+// The load with the device planner: streams and next positions are built in
+// device memory the handle owns; the per-mode tables come back to the host
+// and are uploaded as in the host path.
+spt_status load_device(int32_t nmodes, const int64_t* dims, int64_t nnz, const int32_t* indices,
+                       const float* values, const PlanOptions& po, int copies, hipStream_t s,
+                       spt_tensor_s** out) {
+    spt_tensor_s* t = nullptr;
+    spt_status st = SPT_OK;
+    try {
+        t = new spt_tensor_s();
+        t->N = nmodes;
+        t->nnz = nnz;
+        for (int w = 0; w < nmodes; ++w) t->dims[w] = dims[w];
+        t->copies = copies;
+        if (!spt::choose_layout(nmodes, dims, &t->lay)) {
+            delete t;
+            return fail(SPT_ERR_UNSUPPORTED, "index bits exceed a 32-byte record");
+        }
+        spt::DevicePlan dp;
+        std::string msg;
+        auto persist = [&](size_t bytes) -> void* {
+            uint8_t* p = nullptr;
+            return dalloc(t, &p, bytes, &t->allocs) == SPT_OK ? (void*)p : nullptr;
+        };
+        const spt::DevicePlanError e =
+            spt::build_plan_device(nmodes, dims, nnz, indices, values, po, t->lay, copies, s, persist, &dp, &msg);
+        if (e != spt::DevicePlanError::kNone) {
+            release(t);
+            delete t;
+            const spt_status code = e == spt::DevicePlanError::kRange  ? SPT_ERR_OUT_OF_RANGE
+                                    : e == spt::DevicePlanError::kOom  ? SPT_ERR_OOM
+                                    : e == spt::DevicePlanError::kHip  ? SPT_ERR_HIP
+                                                                       : SPT_ERR_INVALID_ARG;
+            return fail(code, msg);
+        }
+        t->kappa = dp.kappa;
+        t->norm_sq = dp.norm_sq;
+        for (int d = 0; d < nmodes && st == SPT_OK; ++d) {
+            const auto& mp = dp.mode[d];
+            t->nsplit[d] = (int32_t)mp.split_row.size();
+            t->nslots[d] = (int32_t)mp.slot_part.size();
+            t->nempty[d] = (int32_t)mp.empty_rows.size();
+            t->max_load[d] = mp.max_load;
+            if ((st = upload(t, &t->ptr[d], mp.ptr, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->psplit_ptr[d], mp.psplit_ptr, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->psplit_row[d], mp.psplit_row, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->psplit_slot[d], mp.psplit_slot, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->split_row[d], mp.split_row, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->split_ptr[d], mp.split_ptr, s)) != SPT_OK) break;
+            if ((st = upload(t, &t->empty_rows[d], mp.empty_rows, s)) != SPT_OK) break;
+            if (copies)
+                t->rec_mode[d] = dp.rec_mode[d];
+            else
+                t->nxt[d] = dp.nxt[d];
+        }
+        if (st == SPT_OK && !copies) {
+            t->rec[0] = dp.rec0;
+            st = dalloc(t, &t->rec[1], (size_t)std::max<int64_t>(1, nnz) * t->lay.words, &t->allocs);
+        }
+        // the uploads read the plan's host vectors
+        if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess)
+            st = fail(SPT_ERR_HIP, "hipStreamSynchronize after upload");
+        if (st != SPT_OK) {
+            release(t);
+            delete t;
+            return st;
+        }
+        t->order0 = std::move(dp.order0);
+        t->cur = 0;
+        t->cur_mode = 0;
+    } catch (const std::bad_alloc&) {
+        if (t) {
+            release(t);
+            delete t;
+        }
+        return fail(SPT_ERR_OOM, "host allocation failed during preprocessing");
+    }
+    *out = t;
+    return SPT_OK;
+}
+
+}  // namespace
+
 spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
                                const int32_t* indices, const float* values, const spt_opts* opts,
                                void* stream, spt_tensor_t* out) {
@@ -357,11 +445,20 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
     spt_status st = get_opts(opts, &po, &copies);
     if (st != SPT_OK) return st;
     bool range = false;
-    std::string msg = spt::validate(nmodes, dims, nnz, indices, &range);
+    std::string msg = po.prep ? spt::validate_shape(nmodes, dims, nnz, indices, &range)
+                              : spt::validate(nmodes, dims, nnz, indices, &range);
     if (!msg.empty()) return fail(range ? SPT_ERR_OUT_OF_RANGE : SPT_ERR_INVALID_ARG, msg);
     if (nnz > 0 && !values) return fail(SPT_ERR_INVALID_ARG, "values is NULL");
     hipStream_t s = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
+    if (po.prep) {
+        spt_tensor_s* t = nullptr;
+        st = load_device(nmodes, dims, nnz, indices, values, po, copies, s, &t);
+        if (st != SPT_OK) return st;
+        t->prep_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = t;
+        return SPT_OK;
+    }
     spt_tensor_s* t = nullptr;
     try {
         t = new spt_tensor_s();

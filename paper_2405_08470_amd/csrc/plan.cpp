@@ -94,16 +94,15 @@ struct Item {
     int32_t piece;
 };
 
-// Partitions one mode: Alg. 1 over the rows (or their pieces), then the
-// partition and the (partition, row) segment of every nonzero.
-void plan_mode(int d, const int64_t* dims, int64_t nnz, const int32_t* idx, int32_t kappa,
-               int64_t cap, ModePlan& mp, std::vector<int32_t>& seg, int64_t* nseg) {
-    const int64_t I = dims[d];
-    const int32_t* c = idx + (int64_t)d * nnz;
-    std::vector<int64_t> deg(I, 0);
-    for (int64_t e = 0; e < nnz; ++e) ++deg[c[e]];
+}  // namespace
+
+void partition_rows(int64_t I, const int64_t* deg, int32_t kappa, int64_t cap, ModePlan& mp,
+                    RowPieces& rp) {
+    std::vector<int64_t>& piece_base = rp.piece_base;
+    std::vector<int32_t>& piece_part = rp.piece_part;
+    std::vector<int32_t>& piece_seg = rp.piece_seg;
     // items: each vertex, or its pieces when heavier than cap
-    std::vector<int64_t> piece_base(I + 1, 0);
+    piece_base.assign(I + 1, 0);
     for (int64_t i = 0; i < I; ++i) {
         int64_t k = (cap > 0 && deg[i] > cap) ? (deg[i] + cap - 1) / cap : 1;
         piece_base[i + 1] = piece_base[i] + k;
@@ -127,7 +126,7 @@ void plan_mode(int d, const int64_t* dims, int64_t nnz, const int32_t* idx, int3
     using LoadId = std::pair<int64_t, int32_t>;
     std::priority_queue<LoadId, std::vector<LoadId>, std::greater<LoadId>> heap;
     for (int32_t z = 0; z < kappa; ++z) heap.push(LoadId(0, z));
-    std::vector<int32_t> piece_part(nitems);
+    piece_part.assign(nitems, 0);
     mp.loads.assign(kappa, 0);
     for (const Item& it : items) {
         LoadId top = heap.top();
@@ -151,8 +150,8 @@ void plan_mode(int d, const int64_t* dims, int64_t nnz, const int32_t* idx, int3
             pairs.push_back({piece_part[j], (int32_t)i});
     std::sort(pairs.begin(), pairs.end());
     pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
-    *nseg = (int64_t)pairs.size();
-    std::vector<int32_t> piece_seg(nitems);
+    rp.nseg = (int64_t)pairs.size();
+    piece_seg.assign(nitems, 0);
     for (int64_t i = 0; i < I; ++i)
         for (int64_t j = piece_base[i]; j < piece_base[i + 1]; ++j) {
             auto it = std::lower_bound(pairs.begin(), pairs.end(),
@@ -162,23 +161,6 @@ void plan_mode(int d, const int64_t* dims, int64_t nnz, const int32_t* idx, int3
     pairs.clear();
     pairs.shrink_to_fit();
 
-    // partition and segment of every nonzero: its row's piece, pieces taking
-    // the row's nonzeros in input order
-    mp.part.resize(nnz);
-    seg.resize(nnz);
-    std::vector<int64_t> seen(I, 0);
-    for (int64_t e = 0; e < nnz; ++e) {
-        const int32_t i = c[e];
-        const int64_t k = piece_base[i + 1] - piece_base[i];
-        int64_t j = 0;
-        if (k > 1) {
-            const int64_t rank = seen[i]++;
-            const int64_t q = deg[i] / k, rem = deg[i] % k, big = rem * (q + 1);
-            j = rank < big ? rank / (q + 1) : rem + (rank - big) / q;
-        }
-        mp.part[e] = piece_part[piece_base[i] + j];
-        seg[e] = piece_seg[piece_base[i] + j];
-    }
     // split rows: pieces in two or more partitions
     mp.split_row.clear();
     mp.split_ptr.assign(1, 0);
@@ -215,6 +197,40 @@ void plan_mode(int d, const int64_t* dims, int64_t nnz, const int32_t* idx, int3
         if (deg[i] == 0) mp.empty_rows.push_back((int32_t)i);
 }
 
+int64_t piece_of_rank(int64_t deg, int64_t k, int64_t rank) {
+    if (k <= 1) return 0;
+    const int64_t q = deg / k, rem = deg % k, big = rem * (q + 1);
+    return rank < big ? rank / (q + 1) : rem + (rank - big) / q;
+}
+
+namespace {
+
+// Partitions one mode: Alg. 1 over the rows (or their pieces), then the
+// partition and the (partition, row) segment of every nonzero.
+void plan_mode(int d, const int64_t* dims, int64_t nnz, const int32_t* idx, int32_t kappa,
+               int64_t cap, ModePlan& mp, std::vector<int32_t>& seg, int64_t* nseg) {
+    const int64_t I = dims[d];
+    const int32_t* c = idx + (int64_t)d * nnz;
+    std::vector<int64_t> deg(I, 0);
+    for (int64_t e = 0; e < nnz; ++e) ++deg[c[e]];
+    RowPieces rp;
+    partition_rows(I, deg.data(), kappa, cap, mp, rp);
+    *nseg = rp.nseg;
+    const std::vector<int64_t>& piece_base = rp.piece_base;
+    // partition and segment of every nonzero: its row's piece, pieces taking
+    // the row's nonzeros in input order
+    mp.part.resize(nnz);
+    seg.resize(nnz);
+    std::vector<int64_t> seen(I, 0);
+    for (int64_t e = 0; e < nnz; ++e) {
+        const int32_t i = c[e];
+        const int64_t k = piece_base[i + 1] - piece_base[i];
+        const int64_t j = k > 1 ? piece_of_rank(deg[i], k, seen[i]++) : 0;
+        mp.part[e] = rp.piece_part[piece_base[i] + j];
+        seg[e] = rp.piece_seg[piece_base[i] + j];
+    }
+}
+
 }  // namespace
 
 int32_t default_kappa(int64_t nnz) {
@@ -224,6 +240,25 @@ int32_t default_kappa(int64_t nnz) {
 
 std::string validate(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
                      bool* range_error) {
+    std::string m = validate_shape(nmodes, dims, nnz, idx, range_error);
+    if (!m.empty()) return m;
+    for (int w = 0; w < nmodes; ++w) {
+        const int32_t* c = idx + (int64_t)w * nnz;
+        const int64_t I = dims[w];
+        for (int64_t e = 0; e < nnz; ++e) {
+            if (c[e] < 0 || c[e] >= I) {
+                *range_error = true;
+                return "index " + std::to_string(c[e]) + " of nonzero " + std::to_string(e) +
+                       " is outside mode " + std::to_string(w) + " (size " + std::to_string(I) +
+                       ")";
+            }
+        }
+    }
+    return "";
+}
+
+std::string validate_shape(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                           bool* range_error) {
     *range_error = false;
     if (nmodes < 2 || nmodes > kMaxModes) return "nmodes must be in [2, 8]";
     if (!dims) return "dims is NULL";
@@ -239,18 +274,6 @@ std::string validate(int nmodes, const int64_t* dims, int64_t nnz, const int32_t
         return "nnz = " + std::to_string(nnz) + " is outside [0, 2^31)";
     }
     if (nnz > 0 && !idx) return "indices is NULL";
-    for (int w = 0; w < nmodes; ++w) {
-        const int32_t* c = idx + (int64_t)w * nnz;
-        const int64_t I = dims[w];
-        for (int64_t e = 0; e < nnz; ++e) {
-            if (c[e] < 0 || c[e] >= I) {
-                *range_error = true;
-                return "index " + std::to_string(c[e]) + " of nonzero " + std::to_string(e) +
-                       " is outside mode " + std::to_string(w) + " (size " + std::to_string(I) +
-                       ")";
-            }
-        }
-    }
     return "";
 }
 

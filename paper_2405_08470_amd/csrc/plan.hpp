@@ -62,7 +62,29 @@ struct PlanOptions {
     int64_t split_cap = 0;   // 0 -> ceil(nnz/kappa); <0 -> never split
     bool remap_ids = true;   // build orders / remap ids
     bool norm = true;        // compute ||X||^2 of the coalesced tensor
+    int prep = 0;            // 0: host planner, 1: device planner (load only)
 };
+
+// Items of one mode after Alg. 1: rows, or pieces of rows heavier than the
+// cap.  Item j of row i is piece_base[i] + j; its partition and its segment
+// (rank of the distinct (partition, row) pair) are piece_part / piece_seg.
+struct RowPieces {
+    std::vector<int64_t> piece_base;  // [I+1]
+    std::vector<int32_t> piece_part;  // [nitems]
+    std::vector<int32_t> piece_seg;   // [nitems]
+    int64_t nseg = 0;
+};
+
+// Alg. 1 from the degrees of one mode's rows: least-loaded assignment of the
+// items (pieces of at most `cap` nonzeros; cap 0: whole rows), partition
+// loads and offsets, split-row and empty-row tables.  Fills mp (all but
+// part/order/remap) and rp.
+void partition_rows(int64_t I, const int64_t* deg, int32_t kappa, int64_t cap, ModePlan& mp,
+                    RowPieces& rp);
+
+// Piece of the nonzero of input-order rank `rank` within a row of degree
+// `deg` cut into k pieces (the first deg mod k pieces one larger).
+int64_t piece_of_rank(int64_t deg, int64_t k, int64_t rank);
 
 int32_t default_kappa(int64_t nnz);
 
@@ -70,6 +92,10 @@ int32_t default_kappa(int64_t nnz);
 // the failure is an index or size out of range).
 std::string validate(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
                      bool* range_error);
+
+// The checks of validate() that do not read the indices.
+std::string validate_shape(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                           bool* range_error);
 
 // Computes the whole plan.  Throws std::bad_alloc on allocation failure.
 void build_plan(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx,

@@ -37,7 +37,8 @@ class SptError(RuntimeError):
 
 class spt_opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_int32), ("copies", ctypes.c_int32),
-                ("split_cap", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4)]
+                ("split_cap", ctypes.c_int64), ("prep", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class spt_info(ctypes.Structure):
@@ -104,10 +105,13 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(stream))
 
 
-def _opts(kappa: int, split_cap: Optional[int], copies: int) -> spt_opts:
+def _opts(kappa: int, split_cap: Optional[int], copies: int, prep: str = "host") -> spt_opts:
     o = spt_opts()
     o.kappa = int(kappa)
     o.copies = int(copies)
+    if prep not in ("host", "device"):
+        raise ValueError("prep must be 'host' or 'device'")
+    o.prep = 1 if prep == "device" else 0
     # split_cap: None -> default ceil(nnz/kappa); <= 0 -> never split
     o.split_cap = 0 if split_cap is None else (int(split_cap) if split_cap > 0 else -1)
     return o
@@ -154,10 +158,11 @@ class Tensor:
 
 
 def tensor_load_coo(dims, indices, values, kappa: int = 0, split_cap: Optional[int] = None,
-                    copies: int = 0, stream=None) -> Tensor:
+                    copies: int = 0, stream=None, prep: str = "host") -> Tensor:
+    """prep: "host" (planner threads) or "device" (planner kernels)."""
     dims64, idx, val = _host_coo(dims, indices, values)
     out = ctypes.c_void_p()
-    o = _opts(kappa, split_cap, copies)
+    o = _opts(kappa, split_cap, copies, prep)
     _check(lib().spt_tensor_load_coo(len(dims64), dims64.ctypes.data, idx.shape[1], idx.ctypes.data,
                                      val.ctypes.data, ctypes.byref(o), _stream(stream),
                                      ctypes.byref(out)))
