@@ -221,6 +221,8 @@ def main() -> int:
     ap.add_argument("--no-bf16", action="store_true", help="skip phase D")
     ap.add_argument("--no-wide", action="store_true", help="skip phases E and F")
     ap.add_argument("--no-host-prep", action="store_true", help="skip the host-planner load timing")
+    ap.add_argument("--prep", choices=("device", "host"), default="device",
+                    help="planner of the timed tensors (default: device)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     args = ap.parse_args()
 
@@ -252,9 +254,9 @@ def main() -> int:
         prep_host = S.tensor_info(th)["prep_seconds"]
         th.free()
         log(f"host planner load: {prep_host:.2f}s")
-    t = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, prep="device")
+    t = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, prep=args.prep)
     info = S.tensor_info(t)
-    log(f"loaded (device planner): kappa {info['kappa']} record {info['record_bytes']} B prep "
+    log(f"loaded ({args.prep} planner): kappa {info['kappa']} record {info['record_bytes']} B prep "
         f"{info['prep_seconds']:.2f}s max partition {info['max_load']} split rows {info['split_rows']}")
     fac = [torch.from_numpy(np.ascontiguousarray(y)).cuda() for y in Y0]
     outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
@@ -348,7 +350,7 @@ def main() -> int:
     ec_only = None
     ec_only_kernel = None
     if not args.no_ec_only:
-        tc = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, copies=1, prep="device")
+        tc = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, copies=1, prep=args.prep)
         for _ in range(W):
             all_modes(tc, False)
         torch.cuda.synchronize()
@@ -421,7 +423,7 @@ def main() -> int:
             "bf16_gather": bf16,
             "bf16_rank64_4mode": wide_bf16,
             "gradient_rank16_4mode": wide_grad,
-            "prep_seconds_device_planner": round(info["prep_seconds"], 3),
+            f"prep_seconds_{args.prep}_planner": round(info["prep_seconds"], 3),
             "prep_seconds_host_planner": round(prep_host, 3) if prep_host is not None else None,
             "copy_GBps": round(copy_gbps, 1),
             "split_rows": info["split_rows"],

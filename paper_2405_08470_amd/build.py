@@ -26,8 +26,10 @@ HIP_SOURCES = ["ec_kernel.hip", "als_kernels.hip", "grad_kernel.hip", "device_pl
 # otherwise emit v_pk_{add,mul,fma}_f32 from plain float code.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Werror=uninitialized", "-Werror=sometimes-uninitialized", "-Werror=return-type",
              "-I", INCLUDE, "-I", CSRC]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Winit-self", "-Werror=uninitialized",
+              "-Werror=return-type", "-D__HIP_PLATFORM_AMD__",
               "-I", INCLUDE, "-I", CSRC, "-I", os.path.join(ROCM, "include")]
 
 

@@ -7,6 +7,12 @@
 
 #include "kernels.hpp"
 
+// Y = M V^-1 on the FP64 matrix cores (1) or with V^-1 in LDS (0); the
+// matrix-core form waits for a check of the instruction's lane layout.
+#ifndef SPT_SOLVE_MFMA
+#define SPT_SOLVE_MFMA 0
+#endif
+
 namespace spt {
 
 namespace {
@@ -485,7 +491,11 @@ int solve_blocks(int64_t rows) {
 
 void launch_solve_rows(int rank, const float* M, const double* Vinv, int64_t rows, float* Y,
                        double* gpart, double* ipart, hipStream_t s) {
+#if SPT_SOLVE_MFMA
     by_rank<SolveMfma>(rank, dim3(solve_blocks(rows)), dim3(256), s, M, Vinv, rows, Y, gpart, ipart);
+#else
+    by_rank<Solve>(rank, dim3(solve_blocks(rows)), dim3(256), s, M, Vinv, rows, Y, gpart, ipart);
+#endif
 }
 
 void launch_als_finish(int rank, int nmodes, int mode, const double* Gun, const double* Isum,

@@ -65,6 +65,7 @@ struct spt_tensor_s {
     int32_t* split_row[8] = {};
     int32_t* split_ptr[8] = {};
     int32_t* empty_rows[8] = {};
+    int32_t* dsrc[8] = {};        // experimental destination-sorted remap only
     int32_t nsplit[8] = {}, nslots[8] = {}, nempty[8] = {};
     int64_t max_load[8] = {};
     std::vector<int32_t> order0;  // input nonzero at each mode-0 position
@@ -103,6 +104,8 @@ struct spt_tensor_s {
 };
 
 namespace {
+
+[[maybe_unused]] int32_t t_kappa(const Plan& p) { return p.kappa; }
 
 template <typename T>
 spt_status dalloc(spt_tensor_s* t, T** p, size_t count, std::vector<void*>* list) {
@@ -207,6 +210,7 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
     a.rec_in = rec_in;
     a.rec_out = rec_out;
     a.nxt = rec_out ? t->nxt[mode] : nullptr;
+    a.dsrc = rec_out ? t->dsrc[mode] : nullptr;
     a.ptr = t->ptr[mode];
     a.psplit_ptr = t->psplit_ptr[mode];
     a.psplit_row = t->psplit_row[mode];
@@ -501,6 +505,27 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
                 nxt.resize(nnz);
                 spt::next_positions(mp.order.data(), plan.mode[(d + 1) % nmodes].remap.data(), nnz,
                                     nxt.data());
+#if SPT_DR_SORTED
+                {
+                    // slots of each partition in the order of their destinations
+                    std::vector<int32_t> prv(nnz), zsrc(nnz), cur(mp.ptr.begin(), mp.ptr.end() - 1);
+                    for (int64_t p = 0; p < nnz; ++p) prv[nxt[p]] = (int32_t)p;
+                    for (int32_t z = 0; z < t_kappa(plan); ++z)
+                        for (int64_t p = mp.ptr[z]; p < mp.ptr[z + 1]; ++p) zsrc[p] = z;
+                    std::vector<int32_t> dsrc(nnz), ddst(nnz);
+                    for (int64_t o = 0; o < nnz; ++o) {
+                        const int64_t q = cur[zsrc[prv[o]]]++;
+                        dsrc[q] = prv[o];
+                        ddst[q] = (int32_t)o;
+                    }
+                    nxt.swap(ddst);
+                    if ((st = upload(t, &t->dsrc[d], dsrc, s)) != SPT_OK) break;
+                    if (hipStreamSynchronize(s) != hipSuccess) {
+                        st = fail(SPT_ERR_HIP, "hipStreamSynchronize after upload");
+                        break;
+                    }
+                }
+#endif
                 if ((st = upload(t, &t->nxt[d], nxt, s)) != SPT_OK) break;
             }
             // the uploads above read host vectors that are reused next mode

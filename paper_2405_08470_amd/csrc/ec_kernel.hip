@@ -26,6 +26,19 @@
 #ifndef SPT_GATHER_INFLIGHT
 #define SPT_GATHER_INFLIGHT 16
 #endif
+// 0: each record is stored to its next position in the step that fetches it;
+// 1: the wave first finishes its partition's computation, then streams the
+//    partition once more and stores every record (no stores in the gather
+//    loop, whose waits would otherwise also wait for them)
+#ifndef SPT_DR_DEFERRED
+#define SPT_DR_DEFERRED 0
+#endif
+// with SPT_DR_DEFERRED: 1 = the deferred pass walks the partition in the
+// order of the records' destinations (dsrc), so runs of consecutive
+// destinations are stored by consecutive lanes
+#ifndef SPT_DR_SORTED
+#define SPT_DR_SORTED 0
+#endif
 
 namespace spt {
 
@@ -131,15 +144,15 @@ __device__ __forceinline__ void store_vals(float* dst, const float (&v)[V]) {
 // lambda so the per-group state stays in registers.
 #define SPT_EC_STEP(T_ARG, cur, ncur, nxt_rec, nnext) \
     do { \
-        const int t = (T_ARG); \
-        if (t + li < gn) { \
-            if (remap) store_rec<RW>(a.rec_out, ncur, cur); \
+        const int step0 = (T_ARG); \
+        if (step0 + li < gn) { \
+            if (remap_inline) store_rec<RW>(a.rec_out, ncur, cur); \
             decode_all<RW, KIND>(cur, a, stage, lane, seq); \
             stage[N][lane] = rword<RW - 1, RW>(cur); \
             stage[N + 1][lane] = (uint32_t)slot_of((int)stage[mode][lane]); \
         } \
         __syncthreads(); \
-        const int cnt = gn - t; \
+        const int cnt = gn - step0; \
         _Pragma("unroll") \
         for (int kb = 0; kb < L; kb += B) { \
             uint4 y[B][NG]; \
@@ -159,9 +172,9 @@ __device__ __forceinline__ void store_vals(float* dst, const float (&v)[V]) {
                             ((int64_t)c * R + li * V) * FT::kBytes); \
                 } \
             } \
-            if (kb == 0 && t + L + li < gn) { \
-                load_rec<RW>(a.rec_in, gs + t + L + li, nxt_rec); \
-                if (remap) nnext = a.nxt[gs + t + L + li]; \
+            if (kb == 0 && step0 + L + li < gn) { \
+                load_rec<RW>(a.rec_in, gs + step0 + L + li, nxt_rec); \
+                if (remap_inline) nnext = a.nxt[gs + step0 + L + li]; \
             } \
         _Pragma("unroll") \
             for (int b = 0; b < B; ++b) { \
@@ -283,6 +296,7 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     bool first_seg = true;
     const int steps = (int)(q + (rm > 0 ? 1 : 0));
     const bool remap = a.rec_out != nullptr;
+    const bool remap_inline = remap && SPT_DR_DEFERRED == 0;
 
     // factor rows gathered for the group's previous nonzero
     uint32_t last_c[NG];
@@ -316,7 +330,7 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     int32_t na = 0, nb = 0;
     if (li < gn) {
         load_rec<RW>(a.rec_in, gs + li, ra);
-        if (remap) na = a.nxt[gs + li];
+        if (remap_inline) na = a.nxt[gs + li];
     }
     for (int t = 0; t < steps; t += 2 * L) {
         SPT_EC_STEP(t, ra, na, rb, nb);
@@ -375,6 +389,26 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
                 cslot = pslot[1][h];
                 csum = active ? part[1][h][rk] : 0.0f;
             }
+        }
+    }
+
+    // deferred remap: the partition's records, 4 per lane in flight
+    if (remap && SPT_DR_DEFERRED != 0) {
+        const int64_t e = s + n;
+        for (int64_t p0 = s + lane; p0 < e; p0 += 4 * 64) {
+            Rec<RW> r[4];
+            int32_t o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t p = p0 + 64 * k;
+                if (p < e) {
+                    load_rec<RW>(a.rec_in, SPT_DR_SORTED ? (int64_t)a.dsrc[p] : p, r[k]);
+                    o[k] = a.nxt[p];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (p0 + 64 * k < e) store_rec<RW>(a.rec_out, o[k], r[k]);
         }
     }
 }
