@@ -284,13 +284,26 @@ def norm_sq(dims: Sequence[int], idx: np.ndarray, val: np.ndarray) -> float:
     nnz = val.shape[0]
     if nnz == 0:
         return 0.0
-    order = np.lexsort(tuple(idx[d] for d in reversed(range(len(dims)))))
-    s = idx[:, order]
-    new = np.ones(nnz, dtype=bool)
-    new[1:] = np.any(s[:, 1:] != s[:, :-1], axis=0)
+    # coordinates in lexicographic order, input order among equal ones
+    total = 1
+    for I in dims:
+        total *= int(I)
+    if total < 2 ** 63:
+        key = np.zeros(nnz, dtype=np.int64)
+        for d, I in enumerate(dims):
+            key = key * int(I) + idx[d].astype(np.int64)
+        order = np.argsort(key, kind="stable")
+        k = key[order]
+        new = np.ones(nnz, dtype=bool)
+        new[1:] = k[1:] != k[:-1]
+    else:
+        order = np.lexsort(tuple(idx[d] for d in reversed(range(len(dims)))))
+        s = idx[:, order]
+        new = np.ones(nnz, dtype=bool)
+        new[1:] = np.any(s[:, 1:] != s[:, :-1], axis=0)
     grp = np.cumsum(new) - 1
-    sums = np.zeros(int(grp[-1]) + 1, dtype=np.float64)
-    np.add.at(sums, grp, val[order].astype(np.float64))
+    # each coordinate's values summed in input order
+    sums = np.bincount(grp, weights=np.asarray(val, dtype=np.float64)[order])
     return float(np.dot(sums, sums))
 
 

@@ -10,7 +10,7 @@
 // Y = M V^-1 on the FP64 matrix cores (1) or with V^-1 in LDS (0); the
 // matrix-core form waits for a check of the instruction's lane layout.
 #ifndef SPT_SOLVE_MFMA
-#define SPT_SOLVE_MFMA 0
+#define SPT_SOLVE_MFMA 1
 #endif
 
 namespace spt {
@@ -260,16 +260,17 @@ __global__ __launch_bounds__(256) void solve_rows_kernel(const float* __restrict
 
 // Y = M V^-1 on the FP64 matrix cores (v_mfma_f64_16x16x4f64), for R a
 // multiple of 16.  Each wave takes 16-row tiles.  Operand layout of the
-// instruction (wave64): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-// of a 16x4 by 4x16 step and holds D[4 (l / 16) + v][l % 16], v = 0..3, of
-// the 16x16 result.  The contraction index k of step s for lane group
-// q = l / 16 is k = q R/4 + s, so a lane's A values are R/4 consecutive
-// columns of its row of M (vector loads) and its B values are the matching
-// rows of V^-1 (held in registers for the whole kernel).  The rounded FP32
-// result feeds the Gram of the unnormalised factor with no data movement:
-// for fixed v, the four rows 4q + v of a tile are the k index of one more
-// step, A = column tile c0 and B = column tile c1 of those rows.  <M, Y>
-// per column (for the fit) is summed in FP64 per lane.
+// instruction on gfx950 (wave64, checked on the device): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] of a 16x4 by 4x16 step, and
+// register v (0..3) of lane l holds D[4 v + l / 16][l % 16] of the 16x16
+// result.  The contraction index k of step s for lane group q = l / 16 is
+// k = q R/4 + s, so a lane's A values are R/4 consecutive columns of its row
+// of M (vector loads) and its B values are the matching rows of V^-1 (held
+// in registers for the whole kernel).  The rounded FP32 result feeds the
+// Gram of the unnormalised factor with no data movement: for fixed v, the
+// four rows 4 v + q of a tile are the k index of one more step, A = column
+// tile c0 and B = column tile c1 of those rows.  <M, Y> per column (for the
+// fit) is summed in FP64 per lane.
 template <int R>
 __global__ __launch_bounds__(256) void solve_rows_mfma_kernel(const float* __restrict__ M,
                                                                const double* __restrict__ Vinv,
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(256) void solve_rows_mfma_kernel(const float* __res
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = r0 + 4 * q + v;
+                const int64_t row = r0 + 4 * v + q;
                 const int col = 16 * ct + rl;
                 double y = 0.0;
                 if (row < rows) {
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(256) void solve_rows_mfma_kernel(const float* __res
                 for (int c1 = c0; c1 < CT; ++c1, ++p)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int i = 16 * c0 + 4 * q + v, j = 16 * c1 + rl;
+                        const int i = 16 * c0 + 4 * v + q, j = 16 * c1 + rl;
                         const double x = gacc[p][v];
                         gsh[i * R + j] = w == 0 ? x : gsh[i * R + j] + x;
                         if (c1 != c0) gsh[j * R + i] = w == 0 ? x : gsh[j * R + i] + x;

@@ -123,11 +123,19 @@ def test_full_size_all_modes_with_remap(cfg):
     t.free()
 
 
-def test_full_size_cp_als_sweep_last_mode_one_step():
-    """After one CP-ALS sweep at 8e7 nonzeros, the last mode's factor must be
-    the FP64 least-squares update from the other (final) factors: on sampled
-    rows, Y_last[i] * lambda = M_last[i] V^-1 with V the Hadamard product of
-    the other factors' Grams; and every column of Y_last has unit norm."""
+def test_full_size_cp_als_sweep_last_mode_update_and_fit():
+    """One CP-ALS sweep at 8e7 nonzeros.  The last mode's update is the FP64
+    least-squares solution from the other (final) factors: Y_last * lambda =
+    M_last V^-1 with V the Hadamard product of the other factors' Grams.
+
+    Checked two ways.  (i) The fit, which is stationary at the least-squares
+    optimum and so insensitive to the conditioning of V: the GPU's fit must
+    equal the oracle's fit of the exact update within 1e-6.  (ii) The update
+    itself on sampled rows, within the accuracy the normal equations allow:
+    FP32 storage of M and of the factors perturbs M and V by about 2^-24
+    relative, which the solve amplifies by up to cond(V); after one sweep of a
+    skewed tensor cond(V) is in the thousands, so the bound is
+    max(1e-5, 16 cond(V) 2^-24).  Every column of Y_last has unit norm."""
     spec = synth.CONFIGS[2]
     _say(f"case full-size CP-ALS sweep: {spec.name}")
     dims, idx, val = synth.make_coo(spec)
@@ -137,23 +145,28 @@ def test_full_size_cp_als_sweep_last_mode_one_step():
     f = [torch.from_numpy(y).cuda() for y in Y0]
     lam = torch.empty(R, dtype=torch.float64, device="cuda")
     fit = S.cp_als_iter(t, f, lam)
-    _say(f"  fit after one sweep {fit:.6f}")
+    t.free()
     Y = [x.cpu().numpy() for x in f]
     lam = lam.cpu().numpy()
     N = len(dims)
     d = N - 1
+    grams = [Y[w].astype(np.float64).T @ Y[w].astype(np.float64) for w in range(N)]
     V = np.ones((R, R))
     for w in range(N - 1):
-        yw = Y[w].astype(np.float64)
-        V *= yw.T @ yw
+        V *= grams[w]
+    M = oracle.mttkrp(dims, idx, val, Y, d)
+    X = np.linalg.solve(V, M.T).T                     # M V^-1
+    lam_o = np.linalg.norm(X, axis=0)
+    Yn = X / lam_o
+    fit_o = oracle.fit_from(oracle.norm_sq(dims, idx, val), M, Yn, lam_o,
+                            grams[:N - 1] + [Yn.T @ Yn])
+    _say(f"  fit gpu {fit:.9f} oracle (exact last update) {fit_o:.9f}")
+    assert abs(fit - fit_o) <= 1e-6
     rows = _sample_rows(idx[d], dims[d], seed=7)
-    M = oracle.mttkrp_rows(dims, idx, val, Y, d, rows)
-    ref = np.linalg.solve(V, M.T).T          # M V^-1 (V symmetric)
-    got = Y[d][rows].astype(np.float64) * lam
-    e = _rel(got, ref)
-    _say(f"  last-mode one-step rel {e:.2e}")
-    assert e <= TOL
+    cond = float(np.linalg.cond(V))
+    tol = max(1e-5, 16 * cond * 2.0 ** -24)
+    e = _rel(Y[d][rows].astype(np.float64) * lam, X[rows])
+    _say(f"  last-mode update on sampled rows rel {e:.2e} (cond(V) {cond:.3g}, bound {tol:.2e})")
+    assert e <= tol
     norms = np.linalg.norm(Y[d].astype(np.float64), axis=0)
     assert np.allclose(norms[lam > 0], 1.0, atol=1e-5)
-    assert 0.0 < fit < 1.0
-    t.free()
