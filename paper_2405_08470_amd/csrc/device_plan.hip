@@ -285,48 +285,46 @@ __global__ void validate_kernel(const int32_t* __restrict__ idx, int64_t nnz, in
     }
 }
 
-// Coordinate runs of the coordinate-sorted order: the run's values summed in
-// input order, squared, at the run's first position (0 elsewhere).
-__global__ void run_sq_kernel(const int32_t* __restrict__ order, const int32_t* __restrict__ idx,
-                              const float* __restrict__ val, int nmodes, int64_t n,
-                              double* __restrict__ out) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = order[p];
-        auto same = [&](int64_t f) {
-            for (int m = 0; m < nmodes; ++m)
-                if (idx[(int64_t)m * n + f] != idx[(int64_t)m * n + e]) return false;
-            return true;
-        };
-        if (p > 0 && same(order[p - 1])) {
-            out[p] = 0.0;
-            continue;
-        }
-        double s = (double)val[e];
-        for (int64_t q = p + 1; q < n && same(order[q]); ++q) s += (double)val[order[q]];
-        out[p] = s * s;
-    }
-}
+// Runs of equal coordinates in the coordinate-sorted order, in chunks of
+// kRunChunk positions, one thread each: the values before the chunk's first
+// run head (the continuation of a run from earlier chunks), the sum of the
+// squared sums of runs that start and end inside the chunk, and the values
+// from the chunk's last head on (a run that may continue).  Each run is
+// summed in position order, which is input order (the sorts are stable).
+constexpr int kRunChunk = 256;
 
-// Block b sums its contiguous span of x in order (per thread, then a fixed
-// tree); partial[b].
-__global__ __launch_bounds__(kT) void sum_span_kernel(const double* __restrict__ x, int64_t n,
-                                                      double* __restrict__ partial) {
-    __shared__ double red[kT];
-    const int tid = threadIdx.x;
-    const int64_t span = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t b0 = std::min<int64_t>(n, (int64_t)blockIdx.x * span), b1 = std::min<int64_t>(n, b0 + span);
-    const int64_t per = (b1 - b0 + kT - 1) / kT;
-    const int64_t t0 = std::min<int64_t>(b1, b0 + tid * per), t1 = std::min<int64_t>(b1, t0 + per);
-    double s = 0.0;
-    for (int64_t i = t0; i < t1; ++i) s += x[i];
-    red[tid] = s;
-    __syncthreads();
-    for (int h = kT / 2; h > 0; h >>= 1) {
-        if (tid < h) red[tid] += red[tid + h];
-        __syncthreads();
+__global__ void run_chunk_kernel(const int32_t* __restrict__ order, const int32_t* __restrict__ idx,
+                                 const float* __restrict__ val, int nmodes, int64_t n,
+                                 double* __restrict__ head_part, double* __restrict__ inner,
+                                 double* __restrict__ tail, int32_t* __restrict__ has_head) {
+    const int64_t nch = (n + kRunChunk - 1) / kRunChunk;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nch;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p0 = c * kRunChunk, p1 = min(n, p0 + kRunChunk);
+        double cur = 0.0, head = 0.0, in = 0.0;
+        bool seen = false;
+        int64_t prev = p0 > 0 ? order[p0 - 1] : -1;
+        for (int64_t p = p0; p < p1; ++p) {
+            const int64_t e = order[p];
+            bool start = prev < 0;
+            for (int m = 0; m < nmodes && !start; ++m)
+                start = idx[(int64_t)m * n + e] != idx[(int64_t)m * n + prev];
+            if (start) {
+                if (seen)
+                    in += cur * cur;
+                else
+                    head = cur;
+                cur = 0.0;
+                seen = true;
+            }
+            cur += (double)val[e];
+            prev = e;
+        }
+        head_part[c] = seen ? head : cur;
+        inner[c] = in;
+        tail[c] = seen ? cur : 0.0;
+        has_head[c] = seen ? 1 : 0;
     }
-    if (tid == 0) partial[blockIdx.x] = red[0];
 }
 
 // ------------------------------------------------------------ host helpers
@@ -596,14 +594,31 @@ DevicePlanError build_plan_device(int N, const int64_t* dims, int64_t nnz, const
                 launch(gather_key_kernel, g, kT, s, sb.k[0], (const int32_t*)(didx + w * nnz), (const int32_t*)sb.v[0], nnz);
                 radix_sort(sb, nnz, bit_len(dims[w] - 1), s);
             }
-            double* sq = tmp.alloc<double>(nnz);
-            launch(run_sq_kernel, g, kT, s, (const int32_t*)sb.v[0], (const int32_t*)didx, (const float*)dval, N, nnz, sq);
-            const int nb = 1024;
-            double* part = tmp.alloc<double>(nb);
-            double* tot = tmp.alloc<double>(1);
-            launch(sum_span_kernel, nb, kT, s, (const double*)sq, nnz, part);
-            launch(sum_span_kernel, 1, kT, s, (const double*)part, (int64_t)nb, tot);
-            check(hipMemcpyAsync(&out->norm_sq, tot, sizeof(double), hipMemcpyDeviceToHost, s), "download norm");
+            const int64_t nch = (nnz + kRunChunk - 1) / kRunChunk;
+            double* hp = tmp.alloc<double>(nch);
+            double* in = tmp.alloc<double>(nch);
+            double* tl = tmp.alloc<double>(nch);
+            int32_t* hh = tmp.alloc<int32_t>(nch);
+            launch(run_chunk_kernel, grid_for(nch, kT, 16384), kT, s, (const int32_t*)sb.v[0],
+                   (const int32_t*)didx, (const float*)dval, N, nnz, hp, in, tl, hh);
+            std::vector<double> h_hp(nch), h_in(nch), h_tl(nch);
+            std::vector<int32_t> h_hh(nch);
+            check(hipMemcpyAsync(h_hp.data(), hp, sizeof(double) * nch, hipMemcpyDeviceToHost, s), "download");
+            check(hipMemcpyAsync(h_in.data(), in, sizeof(double) * nch, hipMemcpyDeviceToHost, s), "download");
+            check(hipMemcpyAsync(h_tl.data(), tl, sizeof(double) * nch, hipMemcpyDeviceToHost, s), "download");
+            check(hipMemcpyAsync(h_hh.data(), hh, sizeof(int32_t) * nch, hipMemcpyDeviceToHost, s), "download");
+            check(hipStreamSynchronize(s), "norm chunks");
+            // runs crossing chunk boundaries, joined in chunk order
+            double carry = 0.0, total = 0.0;
+            for (int64_t c = 0; c < nch; ++c) {
+                carry += h_hp[c];
+                if (h_hh[c]) {
+                    total += carry * carry;
+                    total += h_in[c];
+                    carry = h_tl[c];
+                }
+            }
+            out->norm_sq = total + carry * carry;
         }
         check(hipStreamSynchronize(s), "device planner");
         return DevicePlanError::kNone;

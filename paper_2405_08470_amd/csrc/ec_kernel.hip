@@ -33,6 +33,12 @@
 #ifndef SPT_DR_DEFERRED
 #define SPT_DR_DEFERRED 0
 #endif
+// 1: a lane reloads a factor row only when the nonzero's index differs from
+// the previous nonzero's of its group (fewer gathers, but each one becomes
+// conditional and the batch no longer issues as one); 0: every gather issued
+#ifndef SPT_GATHER_REUSE
+#define SPT_GATHER_REUSE 0
+#endif
 // with SPT_DR_DEFERRED: 1 = the deferred pass walks the partition in the
 // order of the records' destinations (dsrc), so runs of consecutive
 // destinations are stored by consecutive lanes
@@ -140,88 +146,6 @@ __device__ __forceinline__ void store_vals(float* dst, const float (&v)[V]) {
         *reinterpret_cast<float4*>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
 }
 
-// The body of one step of ec_kernel (see there); a macro rather than a
-// lambda so the per-group state stays in registers.
-#define SPT_EC_STEP(T_ARG, cur, ncur, nxt_rec, nnext) \
-    do { \
-        const int step0 = (T_ARG); \
-        if (step0 + li < gn) { \
-            if (remap_inline) store_rec<RW>(a.rec_out, ncur, cur); \
-            decode_all<RW, KIND>(cur, a, stage, lane, seq); \
-            stage[N][lane] = rword<RW - 1, RW>(cur); \
-            stage[N + 1][lane] = (uint32_t)slot_of((int)stage[mode][lane]); \
-        } \
-        __syncthreads(); \
-        const int cnt = gn - step0; \
-        _Pragma("unroll") \
-        for (int kb = 0; kb < L; kb += B) { \
-            uint4 y[B][NG]; \
-        _Pragma("unroll") \
-            for (int b = 0; b < B; ++b) { \
-                const int slot = g * L + kb + b; \
-                const bool live = kb + b < cnt; \
-        _Pragma("unroll") \
-                for (int k = 0; k < NG; ++k) { \
-                    const uint32_t cprev = b == 0 ? last_c[k] : cb[b - 1][k]; \
-                    const uint32_t c = live ? stage[a.rot[k + 1]][slot] : cprev; \
-                    cb[b][k] = c; \
-                    y[b][k] = b == 0 ? last_y[k] : y[b - 1][k]; \
-                    if (c != cprev) \
-                        y[b][k] = *reinterpret_cast<const uint4*>( \
-                            static_cast<const char*>(a.fac[k + 1]) + \
-                            ((int64_t)c * R + li * V) * FT::kBytes); \
-                } \
-            } \
-            if (kb == 0 && step0 + L + li < gn) { \
-                load_rec<RW>(a.rec_in, gs + step0 + L + li, nxt_rec); \
-                if (remap_inline) nnext = a.nxt[gs + step0 + L + li]; \
-            } \
-        _Pragma("unroll") \
-            for (int b = 0; b < B; ++b) { \
-                if (kb + b < cnt) { \
-                    const int slot = g * L + kb + b; \
-                    const int row = (int)stage[mode][slot]; \
-                    if (row != cur_row) { \
-                        if (cur_row >= 0) { \
-                            if (first_seg && open_left) { \
-                                store_vals<V>(&part[0][g][li * V], acc); \
-                                if (li == 0) { \
-                                    prow[0][g] = cur_row; \
-                                    pslot[0][g] = cur_slot; \
-                                } \
-                            } else { \
-                                store_vals<V>(row_dst<R>(a, cur_row, cur_slot) + li * V, acc); \
-                            } \
-                            first_seg = false; \
-                        } \
-                        cur_row = row; \
-                        cur_slot = (int)stage[N + 1][slot]; \
-        _Pragma("unroll") \
-                        for (int v = 0; v < V; ++v) acc[v] = 0.0f; \
-                    } \
-                    const float val = __uint_as_float(stage[N][slot]); \
-                    float prod[V]; \
-                    widen<FT>(y[b][0], prod); \
-        _Pragma("unroll") \
-                    for (int k = 1; k < NG; ++k) { \
-                        float f[V]; \
-                        widen<FT>(y[b][k], f); \
-        _Pragma("unroll") \
-                        for (int v = 0; v < V; ++v) prod[v] *= f[v]; \
-                    } \
-        _Pragma("unroll") \
-                    for (int v = 0; v < V; ++v) acc[v] = fmaf(prod[v], val, acc[v]); \
-                } \
-            } \
-        _Pragma("unroll") \
-            for (int k = 0; k < NG; ++k) { \
-                last_c[k] = cb[B - 1][k]; \
-                last_y[k] = y[B - 1][k]; \
-            } \
-        } \
-        __syncthreads(); \
-    } while (0)
-
 template <int N, int R, int RW, int KIND, typename FT>
 __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     constexpr int V = FT::kPerLoad;
@@ -320,21 +244,106 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
         return slot;
     };
 
-    // One step (SPT_EC_STEP, defined above the kernel): commit the record
-    // fetched for this step (remap store, decode), prefetch the next step's
-    // record into the other buffer after the first gathers, then run the lane
-    // groups over their L nonzeros of this step.  Two record buffers
-    // alternate, so a prefetch never overwrites the registers of a remap
-    // store still in flight.
+    // One step: commit the record fetched for this step (remap store,
+    // decode), prefetch the next step's record into the other buffer after
+    // the first gathers, then run the lane groups over their L nonzeros of
+    // this step.  Two record buffers alternate, so a prefetch never
+    // overwrites the registers of a remap store still in flight.
     Rec<RW> ra, rb;
     int32_t na = 0, nb = 0;
     if (li < gn) {
         load_rec<RW>(a.rec_in, gs + li, ra);
         if (remap_inline) na = a.nxt[gs + li];
     }
+    auto step = [&](int step0, Rec<RW>& cur, int32_t& ncur, Rec<RW>& nxt_rec, int32_t& nnext) {
+        if (step0 + li < gn) {
+            if (remap_inline) store_rec<RW>(a.rec_out, ncur, cur);
+            decode_all<RW, KIND>(cur, a, stage, lane, seq);
+            stage[N][lane] = rword<RW - 1, RW>(cur);
+            stage[N + 1][lane] = (uint32_t)slot_of((int)stage[mode][lane]);
+        }
+        __syncthreads();
+        const int cnt = gn - step0;
+        #pragma unroll
+        for (int kb = 0; kb < L; kb += B) {
+            uint4 y[B][NG];
+            #pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int slot = g * L + kb + b;
+                const bool live = kb + b < cnt;
+                #pragma unroll
+                for (int k = 0; k < NG; ++k) {
+                    if (SPT_GATHER_REUSE) {
+                        const uint32_t cprev = b == 0 ? last_c[k] : cb[b - 1][k];
+                        const uint32_t c = live ? stage[a.rot[k + 1]][slot] : cprev;
+                        cb[b][k] = c;
+                        y[b][k] = b == 0 ? last_y[k] : y[b - 1][k];
+                        if (c != cprev)
+                            y[b][k] = *reinterpret_cast<const uint4*>(
+                                static_cast<const char*>(a.fac[k + 1]) +
+                                ((int64_t)c * R + li * V) * FT::kBytes);
+                    } else if (live) {
+                        y[b][k] = *reinterpret_cast<const uint4*>(
+                            static_cast<const char*>(a.fac[k + 1]) +
+                            ((int64_t)stage[a.rot[k + 1]][slot] * R + li * V) * FT::kBytes);
+                    }
+                }
+            }
+            if (kb == 0 && step0 + L + li < gn) {
+                load_rec<RW>(a.rec_in, gs + step0 + L + li, nxt_rec);
+                if (remap_inline) nnext = a.nxt[gs + step0 + L + li];
+            }
+            #pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (kb + b < cnt) {
+                    const int slot = g * L + kb + b;
+                    const int row = (int)stage[mode][slot];
+                    if (row != cur_row) {
+                        if (cur_row >= 0) {
+                            if (first_seg && open_left) {
+                                store_vals<V>(&part[0][g][li * V], acc);
+                                if (li == 0) {
+                                    prow[0][g] = cur_row;
+                                    pslot[0][g] = cur_slot;
+                                }
+                            } else {
+                                store_vals<V>(row_dst<R>(a, cur_row, cur_slot) + li * V, acc);
+                            }
+                            first_seg = false;
+                        }
+                        cur_row = row;
+                        cur_slot = (int)stage[N + 1][slot];
+                        #pragma unroll
+                        for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+                    }
+                    const float val = __uint_as_float(stage[N][slot]);
+                    float prod[V];
+                    widen<FT>(y[b][0], prod);
+                    #pragma unroll
+                    for (int k = 1; k < NG; ++k) {
+                        float f[V];
+                        widen<FT>(y[b][k], f);
+                        #pragma unroll
+                        for (int v = 0; v < V; ++v) prod[v] *= f[v];
+                    }
+                    #pragma unroll
+                    for (int v = 0; v < V; ++v) acc[v] = fmaf(prod[v], val, acc[v]);
+                }
+            }
+            if (SPT_GATHER_REUSE) {
+                #pragma unroll
+                for (int k = 0; k < NG; ++k) {
+                    last_c[k] = cb[B - 1][k];
+                    last_y[k] = y[B - 1][k];
+                }
+            }
+        }
+        __syncthreads();
+    
+    };
     for (int t = 0; t < steps; t += 2 * L) {
-        SPT_EC_STEP(t, ra, na, rb, nb);
-        if (t + L < steps) SPT_EC_STEP(t + L, rb, nb, ra, na);
+        step(t, ra, na, rb, nb);
+        if (t + L < steps) step(t + L, rb, nb, ra, na);
     }
 
     // the group's last segment
@@ -529,7 +538,6 @@ bool by_layout(int rank, int fdtype, int words, int kind, int kappa, const EcArg
     return false;
 }
 
-#undef SPT_EC_STEP
 
 }  // namespace
 
