@@ -237,6 +237,32 @@ def phase_gradient(torch, S, synth, K, W):
             "half_noise_sum_sq": noise_half_ss}
 
 
+def ablation(torch, S, dims, idx, val, fac, outs, K, W, name):
+    """The fused all-mode pass across partition counts kappa (the analog of the
+    paper's threadblock-count sweep) and with the heavy-row split off (pure
+    Alg. 1): ms per pass, per-mode EC+remap kernel time, largest partition."""
+    N = len(dims)
+    rows = []
+    settings = [(k, None) for k in (2048, 4096, 8192, 16384, 32768, 65536)] + [(16384, 0)]
+    for kappa, cap in settings:
+        t = S.tensor_load_coo(dims, idx, val, kappa=kappa, split_cap=cap, prep="device")
+        info = S.tensor_info(t)
+
+        def run(tt=t):
+            for d in range(N):
+                S.mttkrp(tt, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
+        kk, ww = (K, W) if cap is None else (1, 0)
+        wall, tm = timed_passes(torch, S, t, kk, ww, run)
+        ec = per_call(tm, "ec_ms", N)
+        t.free()
+        row = {"kappa": kappa, "split": cap is None, "ms_per_pass": round(wall, 4),
+               "ec_remap_kernel_ms": [round(x, 4) for x in ec], "max_partition": info["max_load"],
+               "mean_partition": round(len(val) / kappa, 1)}
+        log(f"ablation {row}")
+        rows.append(row)
+    return {"ablation": name, "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +278,9 @@ def main() -> int:
     ap.add_argument("--no-host-prep", action="store_true", help="skip the host-planner load timing")
     ap.add_argument("--prep", choices=("device", "host"), default="device",
                     help="planner of the timed tensors (default: device)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the benchmark line: the fused pass across kappa and with the "
+                         "heavy-row split off (one JSON line)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     args = ap.parse_args()
 
@@ -289,6 +318,10 @@ def main() -> int:
         f"{info['prep_seconds']:.2f}s max partition {info['max_load']} split rows {info['split_rows']}")
     fac = [torch.from_numpy(np.ascontiguousarray(y)).cuda() for y in Y0]
     outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
+    if args.ablation:
+        t.free()
+        print(json.dumps(ablation(torch, S, dims, idx, val, fac, outs, K, W, spec.name)), flush=True)
+        return 0
 
     def all_modes(tt, fuse):
         for d in range(N):
