@@ -144,7 +144,7 @@ def per_call(tm, key, N):
 
 def phase_bf16_wide(torch, S, synth, K, W):
     """Phase E: FP32 against BF16 factors on the 4-mode rank-64 workload."""
-    spec = synth.CONFIGS[4]
+    spec = synth.WORKLOADS["zipf4_1e8"]
     t0 = time.perf_counter()
     dims, idx, val = synth.make_coo(spec)
     Y = synth.make_factors(spec)
@@ -195,7 +195,7 @@ def planted_values(idx, P, noise):
 
 def phase_gradient(torch, S, synth, K, W):
     """Phase F: gradient of the CP fit over the nonzeros vs plain spMTTKRP."""
-    spec = synth.CONFIGS[5]
+    spec = synth.WORKLOADS["planted4_5e7"]
     t0 = time.perf_counter()
     dims, idx, P, noise = synth.planted_parts(spec)
     val = planted_values(idx, P, noise)
@@ -268,7 +268,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, help="workload id (1-4), default 2")
+    ap.add_argument("--workload", default="zipf3_8e7",
+                    help="uniform3_1e5, zipf3_8e7 (default), zipf5_5e7 or zipf4_1e8")
     ap.add_argument("--nnz", type=int, default=None, help="override the nonzero count")
     ap.add_argument("--kappa", type=int, default=0)
     ap.add_argument("--no-ec-only", action="store_true", help="skip phase C")
@@ -295,7 +296,7 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
-    spec = synth.CONFIGS[args.config]
+    spec = synth.WORKLOADS[args.workload]
     if args.nnz:
         spec = synth.scaled(spec, args.nnz)
     K, W = args.steps, args.warmup

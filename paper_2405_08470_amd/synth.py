@@ -152,18 +152,18 @@ class TensorSpec:
 # The workloads of the benchmark configurations (3-, 4- and 5-mode, uniform
 # and skewed).  Index permutations are applied to every Zipf mode so hot rows
 # do not sit at low ids.
-CONFIGS = {
-    1: TensorSpec("uniform3_1e5", (1000, 800, 600), 100_000, 16,
+WORKLOADS = {
+    "uniform3_1e5": TensorSpec("uniform3_1e5", (1000, 800, 600), 100_000, 16,
                   "uniform_distinct", values="uniform", seed=1, als_iters=5),
-    2: TensorSpec("zipf3_8e7", (100_000, 80_000, 2_000_000), 80_000_000, 32,
+    "zipf3_8e7": TensorSpec("zipf3_8e7", (100_000, 80_000, 2_000_000), 80_000_000, 32,
                   "zipf", 1.1, "uniform", seed=2, als_iters=10),
-    3: TensorSpec("zipf5_5e7", (10_000, 10_000, 5_000, 200, 50), 50_000_000, 32,
+    "zipf5_5e7": TensorSpec("zipf5_5e7", (10_000, 10_000, 5_000, 200, 50), 50_000_000, 32,
                   "zipf", 1.2, "lognormal", seed=3, als_iters=10),
-    4: TensorSpec("zipf4_1e8", (50_000, 50_000, 20_000, 1_000), 100_000_000, 64,
+    "zipf4_1e8": TensorSpec("zipf4_1e8", (50_000, 50_000, 20_000, 1_000), 100_000_000, 64,
                   "zipf", 1.1, "uniform", seed=4, als_iters=10),
     # Observed entries of a planted rank-16 model plus N(0, 0.01^2) noise:
     # the gradient-fit workload.
-    5: TensorSpec("planted4_5e7", (20_000, 20_000, 10_000, 500), 50_000_000, 16,
+    "planted4_5e7": TensorSpec("planted4_5e7", (20_000, 20_000, 10_000, 500), 50_000_000, 16,
                   "uniform_distinct", values="planted", seed=5, als_iters=0,
                   noise_sd=0.01),
 }

@@ -46,14 +46,15 @@ def test_planner_bit_exact_against_oracle(dims, nnz, kappa, cap):
 
 
 def test_planner_bit_exact_on_skewed_workloads():
-    for cfg, nnz, kappa in ((2, 300_000, 96), (3, 200_000, 128), (1, 100_000, 50)):
-        spec = synth.scaled(synth.CONFIGS[cfg], nnz)
+    for name, nnz, kappa in (("zipf3_8e7", 300_000, 96), ("zipf5_5e7", 200_000, 128),
+                             ("uniform3_1e5", 100_000, 50)):
+        spec = synth.scaled(synth.WORKLOADS[name], nnz)
         dims, idx, _ = synth.make_coo(spec)
         p = oracle.plan(dims, idx, kappa)
         q = S.plan_coo(dims, idx, kappa=kappa)
         for d in range(len(dims)):
-            assert np.array_equal(p["b"][d], q["remap"][d]), (cfg, d)
-            assert np.array_equal(p["part"][d], q["part"][d]), (cfg, d)
+            assert np.array_equal(p["b"][d], q["remap"][d]), (name, d)
+            assert np.array_equal(p["part"][d], q["part"][d]), (name, d)
 
 
 def test_planner_default_kappa_and_empty_tensor():

@@ -46,11 +46,12 @@ def _gpu_sweeps(dims, idx, val, Y0, iters, **kw):
     return out
 
 
-@pytest.mark.parametrize("cfg_nnz", [(1, None), (2, 200_000), (3, 150_000)])
-def test_one_sweep_parity(cfg_nnz):
-    cfg, nnz = cfg_nnz
-    spec = synth.CONFIGS[cfg] if nnz is None else synth.scaled(synth.CONFIGS[cfg], nnz)
-    _say("config", cfg, spec.nnz)
+@pytest.mark.parametrize("name_nnz", [("uniform3_1e5", None), ("zipf3_8e7", 200_000),
+                                      ("zipf5_5e7", 150_000)])
+def test_one_sweep_parity(name_nnz):
+    name, nnz = name_nnz
+    spec = synth.WORKLOADS[name] if nnz is None else synth.scaled(synth.WORKLOADS[name], nnz)
+    _say("workload", name, spec.nnz)
     dims, idx, val = synth.make_coo(spec)
     Y0 = synth.make_factors(spec)
     Yg, lg, fg = _gpu_sweeps(dims, idx, val, Y0, 1)
@@ -64,7 +65,7 @@ def test_one_sweep_parity(cfg_nnz):
 
 
 def test_fit_after_five_sweeps_config1():
-    spec = synth.CONFIGS[1]
+    spec = synth.WORKLOADS["uniform3_1e5"]
     dims, idx, val = synth.make_coo(spec)
     Y0 = synth.make_factors(spec)
     _, _, fg = _gpu_sweeps(dims, idx, val, Y0, spec.als_iters)
@@ -74,7 +75,7 @@ def test_fit_after_five_sweeps_config1():
 
 
 def test_one_step_parity_from_a_later_iterate():
-    spec = synth.scaled(synth.CONFIGS[2], 150_000)
+    spec = synth.scaled(synth.WORKLOADS["zipf3_8e7"], 150_000)
     dims, idx, val = synth.make_coo(spec)
     Y0 = synth.make_factors(spec)
     Y3, _, _ = _gpu_sweeps(dims, idx, val, Y0, 3)

@@ -27,10 +27,10 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-CASES = [("zipf4_r64", synth.scaled(synth.CONFIGS[4], 300_000, dims=(5000, 5000, 2000, 100))),
-         ("zipf3_r32", synth.scaled(synth.CONFIGS[2], 300_000, dims=(3000, 2500, 60_000))),
-         ("zipf5_r32", synth.scaled(synth.CONFIGS[3], 200_000)),
-         ("uniform3_r16", synth.CONFIGS[1])]
+CASES = [("zipf4_r64", synth.scaled(synth.WORKLOADS["zipf4_1e8"], 300_000, dims=(5000, 5000, 2000, 100))),
+         ("zipf3_r32", synth.scaled(synth.WORKLOADS["zipf3_8e7"], 300_000, dims=(3000, 2500, 60_000))),
+         ("zipf5_r32", synth.scaled(synth.WORKLOADS["zipf5_5e7"], 200_000)),
+         ("uniform3_r16", synth.WORKLOADS["uniform3_1e5"])]
 
 
 @pytest.mark.parametrize("name,spec", CASES, ids=[c[0] for c in CASES])
@@ -62,7 +62,7 @@ def test_cp_als_with_bf16_gathers_one_sweep():
     # The GPU rounds its FP32 iterates to BF16, the oracle its FP64 ones; the
     # iterates differ by ~1e-6, which flips the rounding of a ~1e-6 / 2^-8
     # fraction of entries by 2^-8 each: ~sqrt(3e-4) * 4e-3 ~ 7e-5 relative.
-    spec = synth.scaled(synth.CONFIGS[4], 200_000, dims=(4000, 4000, 1500, 80))
+    spec = synth.scaled(synth.WORKLOADS["zipf4_1e8"], 200_000, dims=(4000, 4000, 1500, 80))
     dims, idx, val = synth.make_coo(spec)
     Y0 = synth.make_factors(spec)
     t = S.tensor_load_coo(dims, idx, val)

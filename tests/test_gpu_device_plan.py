@@ -117,7 +117,7 @@ def test_device_planner_empty_tensor_and_errors():
 
 @pytest.mark.slow
 def test_device_planner_full_size_3mode():
-    spec = synth.CONFIGS[2]
+    spec = synth.WORKLOADS["zipf3_8e7"]
     _say(f"case device planner at full size: {spec.name}")
     dims, idx, val = synth.make_coo(spec)
     td = S.tensor_load_coo(dims, idx, val, prep="device")

@@ -88,10 +88,10 @@ def _compare(dims, idx, val, Y, outs, cols, label):
         assert e <= TOL
 
 
-@pytest.mark.parametrize("cfg", [2, 3, 4])
-def test_full_size_all_modes_with_remap(cfg):
-    spec = synth.CONFIGS[cfg]
-    _say(f"case full-size config {cfg}: {spec.name} dims {spec.dims} nnz {spec.nnz} R {spec.rank}")
+@pytest.mark.parametrize("name", ["zipf3_8e7", "zipf5_5e7", "zipf4_1e8"])
+def test_full_size_all_modes_with_remap(name):
+    spec = synth.WORKLOADS[name]
+    _say(f"case full-size {spec.name}: dims {spec.dims} nnz {spec.nnz} R {spec.rank}")
     dims, idx, val = synth.make_coo(spec)
     Y = synth.make_factors(spec)
     R = spec.rank
@@ -107,7 +107,7 @@ def test_full_size_all_modes_with_remap(cfg):
     outs = _all_modes(t, dims, fdev, R, check=lambda m: _check_stream(t, idx, val, m))
     cols = list(range(0, R, R // 8))
     _compare(dims, idx, val, Y, outs, cols, "fp32")
-    if cfg == 4:
+    if name == "zipf4_1e8":
         # BF16 factor storage and gathers, FP32 accumulation
         Yb = [oracle.bf16_round(y) for y in Y]
         fb = [f.to(torch.bfloat16) for f in fdev]
@@ -139,7 +139,7 @@ def test_full_size_cp_als_sweep_last_mode_update_and_fit():
     relative, which the solve amplifies by up to cond(V); after one sweep of a
     skewed tensor cond(V) is in the thousands, so the bound is
     max(1e-5, 16 cond(V) 2^-24).  Every column of Y_last has unit norm."""
-    spec = synth.CONFIGS[2]
+    spec = synth.WORKLOADS["zipf3_8e7"]
     _say(f"case full-size CP-ALS sweep: {spec.name}")
     dims, idx, val = synth.make_coo(spec)
     Y0 = synth.make_factors(spec)

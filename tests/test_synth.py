@@ -40,18 +40,18 @@ def test_zipf_rank_frequency_slope():
 
 
 def test_config1_distinct_and_config_shapes():
-    dims, idx, val = synth.make_coo(synth.CONFIGS[1])
+    dims, idx, val = synth.make_coo(synth.WORKLOADS["uniform3_1e5"])
     assert idx.shape == (3, 100_000) and val.dtype == np.float32
     lin = (idx[0].astype(np.int64) * dims[1] + idx[1]) * dims[2] + idx[2]
     assert np.unique(lin).size == 100_000
     for d in range(3):
         assert idx[d].min() >= 0 and idx[d].max() < dims[d]
-    d2, i2, v2 = synth.make_coo(synth.CONFIGS[1])
+    d2, i2, v2 = synth.make_coo(synth.WORKLOADS["uniform3_1e5"])
     assert np.array_equal(idx, i2) and np.array_equal(val, v2)
 
 
 def test_zipf_config_is_skewed_and_shuffled():
-    spec = synth.scaled(synth.CONFIGS[3], 200_000)
+    spec = synth.scaled(synth.WORKLOADS["zipf5_5e7"], 200_000)
     dims, idx, val = synth.make_coo(spec)
     assert np.all(val > 0)  # lognormal values
     for d, I in enumerate(dims):
