@@ -7,8 +7,12 @@ FP32 factors N(0,1) -- synthetic, seeded, shaped like the paper's 3-mode
 recommender / knowledge-base tensors.
 
 Phases (inputs resident in HBM before any timed region):
-  A  all-mode spMTTKRP with the remap fused (mode 0 -> 1 -> 2 -> 0): K timed
+  A  all-mode spMTTKRP with dynamic remapping (mode 0 -> 1 -> 2 -> 0), each
+     mode's elementwise kernel followed by the remap pass that writes each
+     chunk of 4096 consecutive records in destination order: K timed
      passes -> `value` (ms per all-mode pass) and per-kernel event times;
+     then the same passes with the remap fused into the elementwise kernel
+     (every record stored at its next position from inside it);
   B  CP-ALS sweeps (A's work plus the FP64 normal-equation update of every
      factor): K timed steps -> `ms_per_step`;
   C  the same spMTTKRP on one mode-ordered copy per mode (no remapping) ->
@@ -46,14 +50,19 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ec_kernel_zipf3_8e7_traffic.txt")
-KERNEL_SOURCES = ("paper_2405_08470_amd/csrc/ec_kernel.hip", "paper_2405_08470_amd/csrc/kernels.hpp")
+CSRC = "paper_2405_08470_amd/csrc/"
+# kernel family -> (committed counter summary, sources the kernel is built from)
+TRAFFIC = {
+    "ec_kernel": ("ec_kernel_zipf3_8e7_traffic.txt", (CSRC + "ec_kernel.hip", CSRC + "kernels.hpp")),
+    "remap_flat_kernel": ("remap_flat_kernel_zipf3_8e7_traffic.txt",
+                            (CSRC + "dr_staged.hip", CSRC + "kernels.hpp")),
+}
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -64,13 +73,17 @@ def measured_traffic(kernel):
     counter summary (FETCH_SIZE and WRITE_SIZE, scaled by what the counters
     read for a plain copy of known size), or None when the summary is missing
     or was taken on other kernel sources."""
+    fam = kernel.split("<")[0]
+    if fam not in TRAFFIC:
+        return None
+    fname, sources = TRAFFIC[fam]
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(ROOT, "profiles", fname)) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
     vals = dict(l.split("=", 1) for l in lines if "=" in l and not l.startswith("#"))
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash() or vals.get("kernel") != kernel:
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(sources) or vals.get("kernel") != kernel:
         return None
     return float(vals["bytes_per_launch"])
 
@@ -82,6 +95,12 @@ def algorithmic_bytes(dims, nnz, R, rec_bytes, mode, remap):
     per_nnz = rec_bytes + (4 + rec_bytes if remap else 0)
     fac = sum(dims[w] for w in range(len(dims)) if w != mode) * R * 4
     return nnz * per_nnz + fac + dims[mode] * R * 4
+
+
+def remap_bytes(nnz, rec_bytes):
+    """Bytes the remap of one mode must move: read each record and its next
+    position, write the record."""
+    return nnz * (2 * rec_bytes + 4)
 
 
 def copy_bandwidth(torch, gib=4.0, reps=10):
@@ -163,10 +182,12 @@ def phase_bf16_wide(torch, S, synth, K, W):
             for d in range(N):
                 S.mttkrp(t, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
         wall, tm = timed_passes(torch, S, t, K, W, run)
-        ec = per_call(tm, "ec_ms", N)
-        res[name] = {"ms_per_pass": round(wall, 4), "ec_remap_kernel_ms": [round(x, 4) for x in ec]}
+        ec, rm = per_call(tm, "ec_ms", N), per_call(tm, "remap_ms", N)
+        res[name] = {"ms_per_pass": round(wall, 4), "ec_kernel_ms": [round(x, 4) for x in ec],
+                     "remap_kernel_ms": [round(x, 4) for x in rm]}
         keep.append([o.clone() for o in outs])
-        log(f"phase E {name}: {wall:.3f} ms per all-mode pass; kernels {['%.3f' % x for x in ec]} ms")
+        log(f"phase E {name}: {wall:.3f} ms per all-mode pass; EC {['%.3f' % x for x in ec]} ms, "
+            f"remap {['%.3f' % x for x in rm]} ms")
     err = [float(torch.linalg.vector_norm(keep[1][d] - keep[0][d]) / torch.linalg.vector_norm(keep[0][d]))
            for d in range(N)]
     log(f"phase E: BF16 vs FP32 factors, rel diff per mode {['%.2e' % e for e in err]}")
@@ -231,21 +252,25 @@ def phase_gradient(torch, S, synth, K, W):
             "kappa": info["kappa"],
             "gradient_ms": round(wall_g, 4),
             "adjoint_ec_kernel_ms": [round(x, 4) for x in per_call(tm_g, "ec_ms", N)],
+            "adjoint_remap_kernel_ms": [round(x, 4) for x in per_call(tm_g, "remap_ms", N)],
             "plain_fp32_all_mode_ms": round(wall_p, 4),
             "plain_ec_kernel_ms": [round(x, 4) for x in per_call(tm_p, "ec_ms", N)],
+            "plain_remap_kernel_ms": [round(x, 4) for x in per_call(tm_p, "remap_ms", N)],
             "loss_at_start": loss_start, "loss_at_planted": loss_planted,
             "half_noise_sum_sq": noise_half_ss}
 
 
 def ablation(torch, S, dims, idx, val, fac, outs, K, W, name):
-    """The fused all-mode pass across partition counts kappa (the analog of the
-    paper's threadblock-count sweep) and with the heavy-row split off (pure
-    Alg. 1): ms per pass, per-mode EC+remap kernel time, largest partition."""
+    """The all-mode pass across partition counts kappa (the analog of the
+    paper's threadblock-count sweep), with the remap fused into the
+    elementwise kernel instead of staged, and with the heavy-row split off
+    (pure Alg. 1): ms per pass, per-mode kernel times, largest partition."""
     N = len(dims)
     rows = []
-    settings = [(k, None) for k in (2048, 4096, 8192, 16384, 32768, 65536)] + [(16384, 0)]
-    for kappa, cap in settings:
-        t = S.tensor_load_coo(dims, idx, val, kappa=kappa, split_cap=cap, prep="device")
+    settings = [(k, None, "staged") for k in (2048, 4096, 8192, 16384, 32768, 65536)]
+    settings += [(16384, None, "fused"), (16384, 0, "staged")]
+    for kappa, cap, remap in settings:
+        t = S.tensor_load_coo(dims, idx, val, kappa=kappa, split_cap=cap, prep="device", remap=remap)
         info = S.tensor_info(t)
 
         def run(tt=t):
@@ -253,11 +278,11 @@ def ablation(torch, S, dims, idx, val, fac, outs, K, W, name):
                 S.mttkrp(tt, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
         kk, ww = (K, W) if cap is None else (1, 0)
         wall, tm = timed_passes(torch, S, t, kk, ww, run)
-        ec = per_call(tm, "ec_ms", N)
+        ec, rm = per_call(tm, "ec_ms", N), per_call(tm, "remap_ms", N)
         t.free()
-        row = {"kappa": kappa, "split": cap is None, "ms_per_pass": round(wall, 4),
-               "ec_remap_kernel_ms": [round(x, 4) for x in ec], "max_partition": info["max_load"],
-               "mean_partition": round(len(val) / kappa, 1)}
+        row = {"kappa": kappa, "split": cap is None, "remap": remap, "ms_per_pass": round(wall, 4),
+               "ec_kernel_ms": [round(x, 4) for x in ec], "remap_kernel_ms": [round(x, 4) for x in rm],
+               "max_partition": info["max_load"], "mean_partition": round(len(val) / kappa, 1)}
         log(f"ablation {row}")
         rows.append(row)
     return {"ablation": name, "rows": rows}
@@ -273,6 +298,7 @@ def main() -> int:
     ap.add_argument("--nnz", type=int, default=None, help="override the nonzero count")
     ap.add_argument("--kappa", type=int, default=0)
     ap.add_argument("--no-ec-only", action="store_true", help="skip phase C")
+    ap.add_argument("--no-fused", action="store_true", help="skip the fused-remap passes of phase A")
     ap.add_argument("--no-als", action="store_true", help="skip phase B")
     ap.add_argument("--no-bf16", action="store_true", help="skip phase D")
     ap.add_argument("--no-wide", action="store_true", help="skip phases E and F")
@@ -280,8 +306,8 @@ def main() -> int:
     ap.add_argument("--prep", choices=("device", "host"), default="device",
                     help="planner of the timed tensors (default: device)")
     ap.add_argument("--ablation", action="store_true",
-                    help="instead of the benchmark line: the fused pass across kappa and with the "
-                         "heavy-row split off (one JSON line)")
+                    help="instead of the benchmark line: the all-mode pass across kappa, with the "
+                         "remap fused, and with the heavy-row split off (one JSON line)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     args = ap.parse_args()
 
@@ -328,7 +354,7 @@ def main() -> int:
         for d in range(N):
             S.mttkrp(tt, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT if fuse else 0)
 
-    # ---- phase A: all-mode spMTTKRP with the remap fused
+    # ---- phase A: all-mode spMTTKRP with dynamic remapping (staged remap pass)
     for _ in range(W):
         all_modes(t, True)
     torch.cuda.synchronize()
@@ -340,10 +366,26 @@ def main() -> int:
     torch.cuda.synchronize()
     wall_a = (time.perf_counter() - w0) * 1e3 / K
     tm_a = S.timing_control(t, False)
-    ec_ms = [tm_a["ec_ms"][d] / max(1, tm_a["calls"][d]) for d in range(N)]
-    fix_ms = [tm_a["fixup_ms"][d] / max(1, tm_a["calls"][d]) for d in range(N)]
-    log(f"phase A: {wall_a:.3f} ms per all-mode pass; EC+remap kernel per mode {['%.3f' % x for x in ec_ms]} ms, "
-        f"fixup {['%.3f' % x for x in fix_ms]} ms")
+    ec_ms = per_call(tm_a, "ec_ms", N)
+    rm_ms = per_call(tm_a, "remap_ms", N)
+    fix_ms = per_call(tm_a, "fixup_ms", N)
+    log(f"phase A: {wall_a:.3f} ms per all-mode pass; EC kernel per mode {['%.3f' % x for x in ec_ms]} ms, "
+        f"staged remap {['%.3f' % x for x in rm_ms]} ms, fixup {['%.3f' % x for x in fix_ms]} ms")
+
+    # the paper's fused form: every record stored at its next position from
+    # inside the elementwise kernel
+    fused = None
+    if not args.no_fused:
+        tf = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, prep=args.prep, remap="fused")
+
+        def fused_pass():
+            for d in range(N):
+                S.mttkrp(tf, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
+        wall_f, tm_f = timed_passes(torch, S, tf, K, W, fused_pass)
+        tf.free()
+        ec_f = per_call(tm_f, "ec_ms", N)
+        fused = {"ms_per_pass": round(wall_f, 4), "ec_remap_kernel_ms": [round(x, 4) for x in ec_f]}
+        log(f"fused remap: {wall_f:.3f} ms per all-mode pass; EC+remap kernel {['%.3f' % x for x in ec_f]} ms")
 
     # the remap alone (Alg. 3 as a separate scatter kernel), N hops per pass
     def remap_pass():
@@ -353,11 +395,22 @@ def main() -> int:
     log(f"remap alone: {wall_r:.3f} ms per pass of {N} scatters")
 
     rec = info["record_bytes"]
-    bytes_a = [algorithmic_bytes(dims, spec.nnz, R, rec, d, True) for d in range(N)]
-    achieved = sum(bytes_a) / (sum(ec_ms) * 1e-3) / 1e9
+    bytes_ec = [algorithmic_bytes(dims, spec.nnz, R, rec, d, False) for d in range(N)]
+    bytes_rm = remap_bytes(spec.nnz, rec)
+    # the whole step of one mode: elementwise kernel + remap
+    bytes_a = [b + bytes_rm for b in bytes_ec]
+    pass_gbps = sum(bytes_a) / ((sum(ec_ms) + sum(rm_ms)) * 1e-3) / 1e9
     canon = 4 * (2 * N + 1)
     bytes_canon = [spec.nnz * 2 * canon + sum(dims[w] for w in range(N) if w != d) * R * 4 + dims[d] * R * 4
                    for d in range(N)]
+    # the dominant kernel of the pass and its roofline
+    if sum(rm_ms) > sum(ec_ms):
+        kernel = f"remap_flat_kernel<{rec // 4},{S.stage_chunk(rec)}>"
+        dom_bytes, dom_ms = bytes_rm, sum(rm_ms) / N
+    else:
+        kernel = f"ec_kernel<{N},{R},{rec // 4}>"
+        dom_bytes, dom_ms = sum(bytes_ec) / N, sum(ec_ms) / N
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
 
     # ---- phase D: the same passes with BF16 factor gathers (FP32 accumulation)
     bf16 = None
@@ -375,16 +428,17 @@ def main() -> int:
         torch.cuda.synchronize()
         wall_d = (time.perf_counter() - w0) * 1e3 / K
         tm_d = S.timing_control(t, False)
-        ec_d = [tm_d["ec_ms"][d] / max(1, tm_d["calls"][d]) for d in range(N)]
+        ec_d, rm_d = per_call(tm_d, "ec_ms", N), per_call(tm_d, "remap_ms", N)
         err = [float(torch.linalg.vector_norm(outs[d] - ref[d]) / torch.linalg.vector_norm(ref[d]))
                for d in range(N)]
-        bytes_d = [b - (sum(dims[w] for w in range(N) if w != d) * R * 2) for d, b in enumerate(bytes_a)]
-        bf16 = {"ms_per_pass": round(wall_d, 4), "ec_remap_kernel_ms": [round(x, 4) for x in ec_d],
+        bytes_d = [b - (sum(dims[w] for w in range(N) if w != d) * R * 2) for d, b in enumerate(bytes_ec)]
+        bf16 = {"ms_per_pass": round(wall_d, 4), "ec_kernel_ms": [round(x, 4) for x in ec_d],
+                "remap_kernel_ms": [round(x, 4) for x in rm_d],
                 "rel_err_vs_fp32_gather": [float("%.3g" % e) for e in err],
-                "GBps": round(sum(bytes_d) / (sum(ec_d) * 1e-3) / 1e9, 1)}
+                "ec_kernel_GBps": round(sum(bytes_d) / (sum(ec_d) * 1e-3) / 1e9, 1)}
         fac = fac32
         del ref
-        log(f"phase D: BF16 gathers {wall_d:.3f} ms per all-mode pass; kernels "
+        log(f"phase D: BF16 gathers {wall_d:.3f} ms per all-mode pass; EC "
             f"{['%.3f' % x for x in ec_d]} ms; rel err vs FP32 gathers {['%.2e' % e for e in err]}")
 
     # ---- phase B: CP-ALS sweeps
@@ -446,7 +500,6 @@ def main() -> int:
         wide_bf16 = phase_bf16_wide(torch, S, synth, K, W)
         wide_grad = phase_gradient(torch, S, synth, K, W)
 
-    kernel = f"ec_kernel<{N},{R},{rec // 4}>"
     traffic = measured_traffic(kernel)
     line = {
         "metric": METRIC,
@@ -472,18 +525,22 @@ def main() -> int:
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": round(traffic) if traffic is not None else None, "kernel": kernel,
-            "bytes_per_launch": int(sum(bytes_a) / N), "avg_launch_ms": round(sum(ec_ms) / N, 4),
+            "bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(dom_ms, 4),
         },
         "cpu_baseline": cpu,
         "breakdown": {
-            "ec_remap_kernel_ms": [round(x, 4) for x in ec_ms],
+            "ec_kernel_ms": [round(x, 4) for x in ec_ms],
+            "remap_kernel_ms": [round(x, 4) for x in rm_ms],
             "fixup_ms": [round(x, 4) for x in fix_ms],
+            "pass_GBps": round(pass_gbps, 1),
+            "pass_frac": round(pass_gbps / HBM_PEAK_GBPS, 4),
+            "fused_remap": fused,
             "als_dense_ms_per_sweep": round(als_ms, 4) if als_ms is not None else None,
             "ec_only_ms_per_pass": round(ec_only, 4) if ec_only is not None else None,
             "ec_only_kernel_ms": [round(x, 4) for x in ec_only_kernel] if ec_only_kernel else None,
             "remap_share": round(1 - ec_only / wall_a, 4) if ec_only is not None else None,
             "remap_alone_ms_per_pass": round(wall_r, 4),
-            "canonical_record_GBps": round(sum(bytes_canon) / (sum(ec_ms) * 1e-3) / 1e9, 1),
+            "canonical_record_GBps": round(sum(bytes_canon) / ((sum(ec_ms) + sum(rm_ms)) * 1e-3) / 1e9, 1),
             "fit": fit,
             "bf16_gather": bf16,
             "bf16_rank64_4mode": wide_bf16,

@@ -62,7 +62,16 @@ typedef struct spt_opts {
                            orders, remap ids, packing; Alg. 1's assignment
                            stays on the host).  Same tables and streams
                            either way; ||X||^2 up to FP64 summation order  */
-    int32_t reserved[3];/* must be zero                                      */
+    int32_t dr;         /* how a remapping MTTKRP moves the stream to the next
+                           mode's order (Alg. 3), copies == 0 only:
+                           0 = a second pass after the elementwise kernel
+                           that writes each chunk of 4096 consecutive
+                           records (16-byte records; 2048 / 1024 for 32 / 48
+                           bytes) in destination order; the load builds its
+                           tables, 6 bytes per nonzero and mode.  1 = fused: the elementwise kernel stores
+                           every record at its next position.  The next
+                           stream is identical either way                   */
+    int32_t reserved[2];/* must be zero                                      */
 } spt_opts;
 
 /* Summary of a loaded tensor (spt_tensor_info). */
@@ -195,9 +204,11 @@ spt_status spt_tensor_get_records(spt_tensor_t t, int32_t *idx_host, float *val_
 /* Kernel time of the launches made on one tensor (spt_timing_control). */
 typedef struct spt_timing {
     int64_t calls[8];        /* timed spMTTKRP launches per output mode        */
-    double ec_ms[8];         /* fused elementwise (+remap) kernel, summed      */
+    double ec_ms[8];         /* elementwise kernel (+remap when fused), summed */
     double fixup_ms[8];      /* split-row fixup and empty-row fill, summed     */
     double als_ms[8];        /* CP-ALS dense step after that mode's MTTKRP     */
+    double remap_ms[8];      /* staged remap pass (opts.dr == 0), summed;
+                                with dr == 1 the remap is inside ec_ms        */
 } spt_timing;
 
 /*

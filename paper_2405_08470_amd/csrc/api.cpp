@@ -66,6 +66,9 @@ struct spt_tensor_s {
     int32_t* split_ptr[8] = {};
     int32_t* empty_rows[8] = {};
     int32_t* dsrc[8] = {};        // experimental destination-sorted remap only
+    int dr = 0;                   // 0: staged remap pass after EC; 1: remap fused into EC
+    int32_t* ddst[8] = {};        // staged remap tables of mode d -> d+1 (dr == 0)
+    uint16_t* doff[8] = {};
     int32_t nsplit[8] = {}, nslots[8] = {}, nempty[8] = {};
     int64_t max_load[8] = {};
     std::vector<int32_t> order0;  // input nonzero at each mode-0 position
@@ -95,7 +98,7 @@ struct spt_tensor_s {
     // kernel timing
     struct Timed {
         int mode;
-        hipEvent_t ev[4];  // before EC, after EC, after fixup, after ALS step
+        hipEvent_t ev[5];  // before EC, after EC, after staged remap, after fixup, after ALS step
     };
     bool timing = false;
     std::vector<Timed> timed;
@@ -137,11 +140,14 @@ void release(spt_tensor_s* t) {
     t->ws_allocs.clear();
 }
 
-spt_status get_opts(const spt_opts* o, PlanOptions* po, int* copies) {
+spt_status get_opts(const spt_opts* o, PlanOptions* po, int* copies, int* dr) {
     *copies = 0;
+    *dr = 0;
     if (!o) return SPT_OK;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 2; ++k)
         if (o->reserved[k] != 0) return fail(SPT_ERR_INVALID_ARG, "opts.reserved must be zero");
+    if (o->dr != 0 && o->dr != 1) return fail(SPT_ERR_INVALID_ARG, "opts.dr must be 0 or 1");
+    *dr = o->dr;
     if (o->prep != 0 && o->prep != 1) return fail(SPT_ERR_INVALID_ARG, "opts.prep must be 0 or 1");
     po->prep = o->prep;
     if (o->kappa < 0) return fail(SPT_ERR_INVALID_ARG, "opts.kappa must be >= 0");
@@ -206,11 +212,14 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
     spt_status st = ensure_carry(t, rank);
     if (st != SPT_OK) return st;
     const int N = t->N;
+    // the staged pass remaps after EC when its tables exist, else EC stores
+    // each record at its next position itself
+    const bool staged = rec_out && t->ddst[mode];
     spt::EcArgs a{};
     a.rec_in = rec_in;
-    a.rec_out = rec_out;
-    a.nxt = rec_out ? t->nxt[mode] : nullptr;
-    a.dsrc = rec_out ? t->dsrc[mode] : nullptr;
+    a.rec_out = staged ? nullptr : rec_out;
+    a.nxt = a.rec_out ? t->nxt[mode] : nullptr;
+    a.dsrc = a.rec_out ? t->dsrc[mode] : nullptr;
     a.ptr = t->ptr[mode];
     a.psplit_ptr = t->psplit_ptr[mode];
     a.psplit_row = t->psplit_row[mode];
@@ -224,12 +233,19 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
         a.foff[k] = t->lay.off[k];
         a.fmask[k] = (uint32_t)((uint64_t(1) << t->lay.bits[k]) - 1);
     }
-    spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr}};
+    spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr, nullptr}};
     tm.ev[0] = mark(t, s);
     if (!spt::launch_ec(N, rank, fdtype, t->lay.words, t->lay.kind, t->kappa, a, s))
         return fail(SPT_ERR_UNSUPPORTED, "no kernel compiled for this mode count / rank / record size");
     HIPCHK(hipGetLastError());
     tm.ev[1] = mark(t, s);
+    if (staged) {
+        spt::launch_remap_staged(t->lay.words, t->nnz, rec_in, rec_out, t->ddst[mode], t->doff[mode], s);
+        HIPCHK(hipGetLastError());
+        tm.ev[2] = mark(t, s);
+    } else {
+        tm.ev[2] = tm.ev[1];
+    }
     spt::FixupArgs f{};
     f.out = out;
     f.carry = t->carry;
@@ -240,8 +256,8 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
     f.nempty = t->nempty[mode];
     spt::launch_fixup(rank, f, s);
     HIPCHK(hipGetLastError());
-    tm.ev[2] = mark(t, s);
-    if (t->timing && tm.ev[0] && tm.ev[1] && tm.ev[2]) t->timed.push_back(tm);
+    tm.ev[3] = mark(t, s);
+    if (t->timing && tm.ev[0] && tm.ev[1] && tm.ev[2] && tm.ev[3]) t->timed.push_back(tm);
     return SPT_OK;
 }
 
@@ -322,8 +338,8 @@ spt_status spt_plan_coo(int32_t nmodes, const int64_t* dims, int64_t nnz, const 
                         int32_t* kappa_out) {
     g_last_error.clear();
     PlanOptions po;
-    int copies = 0;
-    spt_status st = get_opts(opts, &po, &copies);
+    int copies = 0, dr = 0;
+    spt_status st = get_opts(opts, &po, &copies, &dr);
     if (st != SPT_OK) return st;
     bool range = false;
     std::string msg = spt::validate(nmodes, dims, nnz, indices, &range);
@@ -354,6 +370,21 @@ spt_status spt_plan_coo(int32_t nmodes, const int64_t* dims, int64_t nnz, const 
 }
 
 namespace {
+
+// Staged remap tables of every mode from its next positions (both planners;
+// the tables depend only on nxt_d, so they are identical either way).
+spt_status build_stage_tables(spt_tensor_s* t, hipStream_t s) {
+    if (t->copies || t->dr != 0) return SPT_OK;
+    for (int d = 0; d < t->N; ++d) {
+        spt_status st = dalloc(t, &t->ddst[d], (size_t)t->nnz, &t->allocs);
+        if (st == SPT_OK) st = dalloc(t, &t->doff[d], (size_t)t->nnz, &t->allocs);
+        if (st != SPT_OK) return st;
+        spt::launch_stage_tables(t->lay.words, t->nxt[d], t->nnz, t->ddst[d], t->doff[d], s);
+        HIPCHK(hipGetLastError());
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(SPT_ERR_HIP, "hipStreamSynchronize after the remap tables");
+    return SPT_OK;
+}
 
 // The load with the device planner: streams and next positions are built in
 // device memory the handle owns; the per-mode tables come back to the host
@@ -445,8 +476,8 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
     if (!out) return fail(SPT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     PlanOptions po;
-    int copies = 0;
-    spt_status st = get_opts(opts, &po, &copies);
+    int copies = 0, dr = 0;
+    spt_status st = get_opts(opts, &po, &copies, &dr);
     if (st != SPT_OK) return st;
     bool range = false;
     std::string msg = po.prep ? spt::validate_shape(nmodes, dims, nnz, indices, &range)
@@ -459,6 +490,12 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
         spt_tensor_s* t = nullptr;
         st = load_device(nmodes, dims, nnz, indices, values, po, copies, s, &t);
         if (st != SPT_OK) return st;
+        t->dr = dr;
+        if ((st = build_stage_tables(t, s)) != SPT_OK) {
+            release(t);
+            delete t;
+            return st;
+        }
         t->prep_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         *out = t;
         return SPT_OK;
@@ -549,6 +586,12 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
         t->order0 = plan.mode[0].order;
         t->cur = 0;
         t->cur_mode = 0;
+        t->dr = dr;
+        if ((st = build_stage_tables(t, s)) != SPT_OK) {
+            release(t);
+            delete t;
+            return st;
+        }
     } catch (const std::bad_alloc&) {
         if (t) {
             release(t);
@@ -567,13 +610,15 @@ spt_status spt_timing_control(spt_tensor_t t, int32_t enable, spt_timing* out) {
     if (out) {
         std::memset(out, 0, sizeof(*out));
         for (const auto& tm : t->timed) {
-            HIPCHK(hipEventSynchronize(tm.ev[3] ? tm.ev[3] : tm.ev[2]));
-            float a = 0.f, b = 0.f, c = 0.f;
+            HIPCHK(hipEventSynchronize(tm.ev[4] ? tm.ev[4] : tm.ev[3]));
+            float a = 0.f, r = 0.f, b = 0.f, c = 0.f;
             HIPCHK(hipEventElapsedTime(&a, tm.ev[0], tm.ev[1]));
-            HIPCHK(hipEventElapsedTime(&b, tm.ev[1], tm.ev[2]));
-            if (tm.ev[3]) HIPCHK(hipEventElapsedTime(&c, tm.ev[2], tm.ev[3]));
+            if (tm.ev[2] != tm.ev[1]) HIPCHK(hipEventElapsedTime(&r, tm.ev[1], tm.ev[2]));
+            HIPCHK(hipEventElapsedTime(&b, tm.ev[2], tm.ev[3]));
+            if (tm.ev[4]) HIPCHK(hipEventElapsedTime(&c, tm.ev[3], tm.ev[4]));
             out->calls[tm.mode] += 1;
             out->ec_ms[tm.mode] += a;
+            out->remap_ms[tm.mode] += r;
             out->fixup_ms[tm.mode] += b;
             out->als_ms[tm.mode] += c;
         }
@@ -700,8 +745,8 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
         spt::launch_scale_cols(rank, (float*)factors[d], t->dims[d], lambda, s);
         if (bf16) spt::launch_to_bf16((const float*)factors[d], t->shadow[d], t->dims[d] * rank, s);
         HIPCHK(hipGetLastError());
-        if (t->timing && !t->timed.empty() && t->timed.back().mode == d && !t->timed.back().ev[3])
-            t->timed.back().ev[3] = mark(t, s);
+        if (t->timing && !t->timed.empty() && t->timed.back().mode == d && !t->timed.back().ev[4])
+            t->timed.back().ev[4] = mark(t, s);
     }
     if (t->copies) t->cur_mode = 0;
     HIPCHK(hipMemcpyAsync(t->status_host, t->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));

@@ -1,0 +1,209 @@
+// Dynamic remapping (Alg. 3) as its own pass, chunk by chunk in destination
+// order.
+//
+// The fused form stores each record at its next-mode position while the
+// elementwise computation runs (one 16-byte store to a random address per
+// nonzero).  Here the stream is cut into chunks of C consecutive records, and
+// the records of each chunk are written in the order of their destinations:
+// consecutive threads take consecutive table slots, so records of one chunk
+// that land next to each other in the next mode's stream go out in the same
+// store instruction and share memory transactions.  Each chunk (64 KB of
+// records) is read in that order too; its lines are fetched once and then hit
+// in L2.  The next mode's stream is the same as the fused form's, bit for bit.
+//
+// Tables (built once at load, per mode d, from the next positions nxt_d):
+//   ddst[c*C + j] = j-th smallest destination among the records of chunk c
+//   doff[c*C + j] = offset inside chunk c of the record that goes there
+// Destinations are distinct (nxt_d is a permutation), so the sorted order is
+// unique and does not depend on how it is computed.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+// Build options (measurement only; the defaults are the measured best):
+//   SPT_STAGE_CHUNK16   records per chunk for 16-byte records (32-byte: half,
+//                       48-byte: a quarter); a power of two
+//   SPT_STAGE_FORM      0: one record per thread over the whole grid, read
+//                       from L2; 1: one workgroup per chunk, staged in LDS
+//                       with coalesced reads; 2: one workgroup per chunk,
+//                       read from L2
+//   SPT_STAGE_THREADS   threads per workgroup of the remap pass
+#ifndef SPT_STAGE_CHUNK16
+#define SPT_STAGE_CHUNK16 4096
+#endif
+#ifndef SPT_STAGE_FORM
+#define SPT_STAGE_FORM 0
+#endif
+#ifndef SPT_STAGE_THREADS
+#define SPT_STAGE_THREADS 256
+#endif
+
+namespace spt {
+namespace {
+
+constexpr int kStageThreads = 256;  // table sort
+constexpr int kRemapThreads = SPT_STAGE_THREADS;
+constexpr int kChunk16 = SPT_STAGE_CHUNK16;
+static_assert((kChunk16 & (kChunk16 - 1)) == 0 && kChunk16 >= 1024 && kChunk16 <= 16384, "chunk");
+static_assert(SPT_STAGE_FORM != 1 || kChunk16 <= 4096, "a staged chunk must fit 64 KB of LDS");
+
+// One workgroup per chunk: bitonic sort of (destination, offset) pairs in LDS.
+template <int C>
+__global__ __launch_bounds__(kStageThreads) void stage_tables_kernel(const int32_t* __restrict__ nxt,
+                                                                      int64_t nnz, int32_t* __restrict__ ddst,
+                                                                      uint16_t* __restrict__ doff) {
+    __shared__ int32_t key[C];
+    __shared__ uint16_t pay[C];
+    const int64_t base = (int64_t)blockIdx.x * C;
+    const int cnt = (int)((nnz - base) < C ? (nnz - base) : C);
+    for (int i = threadIdx.x; i < C; i += kStageThreads) {
+        key[i] = i < cnt ? nxt[base + i] : INT_MAX;  // padding sorts last
+        pay[i] = (uint16_t)i;
+    }
+    __syncthreads();
+    for (int k = 2; k <= C; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < C; i += kStageThreads) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool ascending = (i & k) == 0;
+                    const int32_t a = key[i], b = key[l];
+                    if ((a > b) == ascending) {
+                        key[i] = b;
+                        key[l] = a;
+                        const uint16_t t = pay[i];
+                        pay[i] = pay[l];
+                        pay[l] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < cnt; i += kStageThreads) {
+        ddst[base + i] = key[i];
+        doff[base + i] = pay[i];
+    }
+}
+
+// One record per thread: slot j of the tables, read from its chunk in L2.
+template <int RW, int C>
+__global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_t* __restrict__ in,
+                                                                    uint32_t* __restrict__ out,
+                                                                    const int32_t* __restrict__ ddst,
+                                                                    const uint16_t* __restrict__ doff,
+                                                                    int64_t nnz) {
+    constexpr int Q = RW / 4;
+    const int64_t j = (int64_t)blockIdx.x * kRemapThreads + threadIdx.x;
+    if (j >= nnz) return;
+    const int64_t p = (j / C) * C + doff[j];
+    const int64_t q = ddst[j];
+    const uint4* src = reinterpret_cast<const uint4*>(in);
+    uint4* dst = reinterpret_cast<uint4*>(out);
+#pragma unroll
+    for (int w = 0; w < Q; ++w) dst[q * Q + w] = src[p * Q + w];
+}
+
+// One workgroup per chunk of C records of RW 32-bit words.
+template <int RW, int C>
+__global__ __launch_bounds__(kRemapThreads) void remap_staged_kernel(const uint32_t* __restrict__ in,
+                                                                      uint32_t* __restrict__ out,
+                                                                      const int32_t* __restrict__ ddst,
+                                                                      const uint16_t* __restrict__ doff,
+                                                                      int64_t nnz) {
+    constexpr int Q = RW / 4;  // 16-byte words per record
+    const int64_t base = (int64_t)blockIdx.x * C;
+    const int cnt = (int)((nnz - base) < C ? (nnz - base) : C);
+    const uint4* src = reinterpret_cast<const uint4*>(in) + base * Q;
+#if SPT_STAGE_FORM == 1
+    constexpr int PER = C * Q / kRemapThreads;
+    __shared__ uint4 buf[C * Q];
+    if (cnt == C) {
+        uint4 v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) v[k] = src[k * kRemapThreads + threadIdx.x];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) buf[k * kRemapThreads + threadIdx.x] = v[k];
+    } else {
+        for (int i = threadIdx.x; i < cnt * Q; i += kRemapThreads) buf[i] = src[i];
+    }
+    __syncthreads();
+#else
+    const uint4* buf = src;  // the chunk is read in destination order; its lines stay in L2
+#endif
+    uint4* dst = reinterpret_cast<uint4*>(out);
+    constexpr int U = 4;
+    for (int j0 = 0; j0 < cnt; j0 += U * kRemapThreads) {
+        int32_t q[U];
+        int o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * kRemapThreads + (int)threadIdx.x;
+            q[u] = j < cnt ? ddst[base + j] : -1;
+            o[u] = j < cnt ? (int)doff[base + j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (q[u] < 0) continue;
+#pragma unroll
+            for (int w = 0; w < Q; ++w) dst[(int64_t)q[u] * Q + w] = buf[o[u] * Q + w];
+        }
+    }
+}
+
+}  // namespace
+
+int stage_chunk(int words) {
+    // 64 KB of LDS per workgroup at most; a power of two for the bitonic sort
+    return words == 4 ? kChunk16 : words == 8 ? kChunk16 / 2 : kChunk16 / 4;
+}
+
+void launch_stage_tables(int words, const int32_t* nxt, int64_t nnz, int32_t* ddst, uint16_t* doff,
+                         hipStream_t s) {
+    if (nnz == 0) return;
+    const int C = stage_chunk(words);
+    const unsigned blocks = (unsigned)((nnz + C - 1) / C);
+    if (C == kChunk16)
+        hipLaunchKernelGGL(stage_tables_kernel<kChunk16>, dim3(blocks), dim3(kStageThreads), 0, s, nxt, nnz, ddst,
+                           doff);
+    else if (C == kChunk16 / 2)
+        hipLaunchKernelGGL(stage_tables_kernel<kChunk16 / 2>, dim3(blocks), dim3(kStageThreads), 0, s, nxt, nnz,
+                           ddst, doff);
+    else
+        hipLaunchKernelGGL(stage_tables_kernel<kChunk16 / 4>, dim3(blocks), dim3(kStageThreads), 0, s, nxt, nnz,
+                           ddst, doff);
+}
+
+void launch_remap_staged(int words, int64_t nnz, const uint32_t* in, uint32_t* out, const int32_t* ddst,
+                         const uint16_t* doff, hipStream_t s) {
+    if (nnz == 0) return;
+    const int C = stage_chunk(words);
+#if SPT_STAGE_FORM == 0
+    const unsigned fblocks = (unsigned)((nnz + kRemapThreads - 1) / kRemapThreads);
+    if (words == 4)
+        hipLaunchKernelGGL((remap_flat_kernel<4, kChunk16>), dim3(fblocks), dim3(kRemapThreads), 0, s, in, out,
+                           ddst, doff, nnz);
+    else if (words == 8)
+        hipLaunchKernelGGL((remap_flat_kernel<8, kChunk16 / 2>), dim3(fblocks), dim3(kRemapThreads), 0, s, in,
+                           out, ddst, doff, nnz);
+    else
+        hipLaunchKernelGGL((remap_flat_kernel<12, kChunk16 / 4>), dim3(fblocks), dim3(kRemapThreads), 0, s, in,
+                           out, ddst, doff, nnz);
+    return;
+#endif
+    const unsigned blocks = (unsigned)((nnz + C - 1) / C);
+    if (words == 4)
+        hipLaunchKernelGGL((remap_staged_kernel<4, kChunk16>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out,
+                           ddst, doff, nnz);
+    else if (words == 8)
+        hipLaunchKernelGGL((remap_staged_kernel<8, kChunk16 / 2>), dim3(blocks), dim3(kRemapThreads), 0, s, in,
+                           out, ddst, doff, nnz);
+    else
+        hipLaunchKernelGGL((remap_staged_kernel<12, kChunk16 / 4>), dim3(blocks), dim3(kRemapThreads), 0, s, in,
+                           out, ddst, doff, nnz);
+}
+
+}  // namespace spt

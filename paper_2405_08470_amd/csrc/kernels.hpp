@@ -65,6 +65,15 @@ void launch_fixup(int rank, const FixupArgs& a, hipStream_t s);
 // following `hops` next-position arrays (nxt[0] first).
 void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,
                   const int32_t* const* nxt, int hops, hipStream_t s);
+// Staged remapping (dr_staged.hip): records in chunks of stage_chunk(words)
+// consecutive stream positions; per chunk, the destinations in increasing
+// order (ddst) and the offset inside the chunk of the record for each (doff).
+int stage_chunk(int words);
+void launch_stage_tables(int words, const int32_t* nxt, int64_t nnz, int32_t* ddst, uint16_t* doff,
+                         hipStream_t s);
+// out[ddst[j]] = in[chunk(j) * C + doff[j]] for every j < nnz
+void launch_remap_staged(int words, int64_t nnz, const uint32_t* in, uint32_t* out, const int32_t* ddst,
+                         const uint16_t* doff, hipStream_t s);
 
 // ---- CP-ALS dense step (FP64 for everything R x R) ----
 int gram_blocks(int64_t rows);

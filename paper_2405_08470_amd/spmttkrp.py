@@ -38,7 +38,7 @@ class SptError(RuntimeError):
 class spt_opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_int32), ("copies", ctypes.c_int32),
                 ("split_cap", ctypes.c_int64), ("prep", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("dr", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class spt_info(ctypes.Structure):
@@ -52,7 +52,8 @@ class spt_info(ctypes.Structure):
 
 class spt_timing(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_int64 * 8), ("ec_ms", ctypes.c_double * 8),
-                ("fixup_ms", ctypes.c_double * 8), ("als_ms", ctypes.c_double * 8)]
+                ("fixup_ms", ctypes.c_double * 8), ("als_ms", ctypes.c_double * 8),
+                ("remap_ms", ctypes.c_double * 8)]
 
 
 EXPORTS = ["spt_tensor_load_coo", "spt_remap_for_mode", "spt_mttkrp", "spt_cp_als_iter",
@@ -105,13 +106,17 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(stream))
 
 
-def _opts(kappa: int, split_cap: Optional[int], copies: int, prep: str = "host") -> spt_opts:
+def _opts(kappa: int, split_cap: Optional[int], copies: int, prep: str = "host",
+          remap: str = "staged") -> spt_opts:
     o = spt_opts()
     o.kappa = int(kappa)
     o.copies = int(copies)
     if prep not in ("host", "device"):
         raise ValueError("prep must be 'host' or 'device'")
     o.prep = 1 if prep == "device" else 0
+    if remap not in ("staged", "fused"):
+        raise ValueError("remap must be 'staged' or 'fused'")
+    o.dr = 0 if remap == "staged" else 1
     # split_cap: None -> default ceil(nnz/kappa); <= 0 -> never split
     o.split_cap = 0 if split_cap is None else (int(split_cap) if split_cap > 0 else -1)
     return o
@@ -158,11 +163,13 @@ class Tensor:
 
 
 def tensor_load_coo(dims, indices, values, kappa: int = 0, split_cap: Optional[int] = None,
-                    copies: int = 0, stream=None, prep: str = "host") -> Tensor:
-    """prep: "host" (planner threads) or "device" (planner kernels)."""
+                    copies: int = 0, stream=None, prep: str = "host", remap: str = "staged") -> Tensor:
+    """prep: "host" (planner threads) or "device" (planner kernels).
+    remap: "staged" (a remap pass after the elementwise kernel) or "fused"
+    (the elementwise kernel stores each record at its next position)."""
     dims64, idx, val = _host_coo(dims, indices, values)
     out = ctypes.c_void_p()
-    o = _opts(kappa, split_cap, copies, prep)
+    o = _opts(kappa, split_cap, copies, prep, remap)
     _check(lib().spt_tensor_load_coo(len(dims64), dims64.ctypes.data, idx.shape[1], idx.ctypes.data,
                                      val.ctypes.data, ctypes.byref(o), _stream(stream),
                                      ctypes.byref(out)))
@@ -275,6 +282,11 @@ def cp_fit_loss(t: Tensor, factors: Sequence[torch.Tensor]) -> torch.Tensor:
     return CPFitLoss.apply(t, *factors)
 
 
+def stage_chunk(record_bytes: int) -> int:
+    """Records per chunk of the staged remap (opts.dr = 0) for a record size."""
+    return {16: 4096, 32: 2048, 48: 1024}[int(record_bytes)]
+
+
 def tensor_info(t: Tensor) -> Dict[str, object]:
     i = spt_info()
     _check(lib().spt_tensor_info(t.handle, ctypes.byref(i)))
@@ -310,7 +322,8 @@ def timing_control(t: Tensor, enable: bool, want: bool = True) -> Optional[Dict[
         return None
     N = t.nmodes
     return {"calls": list(tm.calls[:N]), "ec_ms": list(tm.ec_ms[:N]),
-            "fixup_ms": list(tm.fixup_ms[:N]), "als_ms": list(tm.als_ms[:N])}
+            "fixup_ms": list(tm.fixup_ms[:N]), "als_ms": list(tm.als_ms[:N]),
+            "remap_ms": list(tm.remap_ms[:N])}
 
 
 def tensor_free(t: Tensor) -> None:
