@@ -68,11 +68,11 @@ def kernel_source_hash(sources):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, kappa):
     """HBM-side bytes per launch of the kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, scaled by what the counters
     read for a plain copy of known size), or None when the summary is missing
-    or was taken on other kernel sources."""
+    or was taken on other kernel sources or another partition count."""
     fam = kernel.split("<")[0]
     if fam not in TRAFFIC:
         return None
@@ -83,7 +83,8 @@ def measured_traffic(kernel):
     except OSError:
         return None
     vals = dict(l.split("=", 1) for l in lines if "=" in l and not l.startswith("#"))
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash(sources) or vals.get("kernel") != kernel:
+    if (vals.get("kernel_source_sha256_16") != kernel_source_hash(sources) or vals.get("kernel") != kernel
+            or vals.get("kappa") != str(kappa)):
         return None
     return float(vals["bytes_per_launch"])
 
@@ -268,7 +269,7 @@ def ablation(torch, S, dims, idx, val, fac, outs, K, W, name):
     N = len(dims)
     rows = []
     settings = [(k, None, "staged") for k in (2048, 4096, 8192, 16384, 32768, 65536)]
-    settings += [(16384, None, "fused"), (16384, 0, "staged")]
+    settings += [(8192, None, "fused"), (8192, 0, "staged")]
     for kappa, cap, remap in settings:
         t = S.tensor_load_coo(dims, idx, val, kappa=kappa, split_cap=cap, prep="device", remap=remap)
         info = S.tensor_info(t)
@@ -500,7 +501,7 @@ def main() -> int:
         wide_bf16 = phase_bf16_wide(torch, S, synth, K, W)
         wide_grad = phase_gradient(torch, S, synth, K, W)
 
-    traffic = measured_traffic(kernel)
+    traffic = measured_traffic(kernel, info["kappa"])
     line = {
         "metric": METRIC,
         "value": round(wall_a, 4),

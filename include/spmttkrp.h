@@ -50,7 +50,7 @@ typedef struct spt_tensor_s *spt_tensor_t;  /* opaque, owned by the library */
 typedef struct spt_opts {
     int32_t kappa;      /* partitions per mode (kappa of Alg. 1) = workgroups
                            of each mode's kernel; 0 = default:
-                           clamp(ceil(nnz / 2048), 1, 16384)                  */
+                           clamp(ceil(nnz / 2048), 1, 8192)                   */
     int32_t copies;     /* 0 = one tensor copy plus its remapping target
                            (the paper's dynamic remapping); 1 = one
                            mode-ordered copy per mode, no remapping needed  */
