@@ -116,8 +116,11 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t *dims, int64_t nnz,
 
 /*
  * spt_remap_for_mode -- reorder the stream into `mode`'s order (dynamic
- * remapping, Sec. 3.1) by following each nonzero's remap ids; one scatter.
- * No effect if the stream is already in that order.  Errors: INVALID_ARG.
+ * remapping, Sec. 3.1) by following each nonzero's remap ids; one pass over
+ * the stream (from the current mode to the next with opts.dr == 0: the
+ * chunk-ordered remap pass; otherwise a scatter along the chained next
+ * positions).  No effect if the stream is already in that order.
+ * Errors: INVALID_ARG.
  */
 spt_status spt_remap_for_mode(spt_tensor_t t, int32_t mode, void *stream);
 

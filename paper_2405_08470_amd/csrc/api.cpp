@@ -304,6 +304,15 @@ spt_status do_remap(spt_tensor_s* t, int mode, hipStream_t s) {
     const int N = t->N;
     const int hops = (mode - t->cur_mode + N) % N;
     if (hops == 0) return SPT_OK;
+    if (hops == 1 && t->ddst[t->cur_mode]) {
+        // one hop: the chunk-ordered remap pass
+        spt::launch_remap_staged(t->lay.words, t->nnz, t->rec[t->cur], t->rec[1 - t->cur], t->ddst[t->cur_mode],
+                                 t->doff[t->cur_mode], s);
+        HIPCHK(hipGetLastError());
+        t->cur = 1 - t->cur;
+        t->cur_mode = mode;
+        return SPT_OK;
+    }
     const int32_t* chain[8];
     for (int h = 0; h < hops; ++h) chain[h] = t->nxt[(t->cur_mode + h) % N];
     spt::launch_remap(t->lay.words, t->nnz, t->rec[t->cur], t->rec[1 - t->cur], chain, hops, s);

@@ -76,3 +76,39 @@ def test_planner_rejects_bad_input(dims, idx, name):
         S.plan_coo(dims, np.array(idx, dtype=np.int32))
     assert ei.value.name == name
     assert ei.value.message
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("dr", 2, "opts.dr must be 0 or 1"),
+    ("dr", -1, "opts.dr must be 0 or 1"),
+    ("prep", 2, "opts.prep must be 0 or 1"),
+    ("copies", 3, "opts.copies must be 0 or 1"),
+])
+def test_options_are_validated_before_any_device_work(field, value, msg):
+    import ctypes
+    o = S._opts(0, None, 0)
+    setattr(o, field, value)
+    dims = np.array([4, 3, 2], dtype=np.int64)
+    idx = np.zeros((3, 1), dtype=np.int32)
+    k = ctypes.c_int32()
+    st = S.lib().spt_plan_coo(3, dims.ctypes.data, 1, idx.ctypes.data, ctypes.byref(o), None, None, None,
+                              ctypes.byref(k))
+    assert S._STATUS[st] == "SPT_ERR_INVALID_ARG"
+    assert S.lib().spt_last_error().decode() == msg
+
+
+def test_options_reserved_words_must_be_zero_and_remap_forms_map():
+    import ctypes
+    o = S._opts(0, None, 0)
+    o.reserved[1] = 1
+    dims = np.array([4, 3, 2], dtype=np.int64)
+    idx = np.zeros((3, 1), dtype=np.int32)
+    k = ctypes.c_int32()
+    st = S.lib().spt_plan_coo(3, dims.ctypes.data, 1, idx.ctypes.data, ctypes.byref(o), None, None, None,
+                              ctypes.byref(k))
+    assert S._STATUS[st] == "SPT_ERR_INVALID_ARG"
+    assert S._opts(0, None, 0, remap="staged").dr == 0
+    assert S._opts(0, None, 0, remap="fused").dr == 1
+    with pytest.raises(ValueError):
+        S._opts(0, None, 0, remap="pull")
+    assert [S.stage_chunk(b) for b in (16, 32, 48)] == [4096, 2048, 1024]

@@ -1,14 +1,15 @@
 """The two forms of dynamic remapping (Alg. 3) against each other on the GPU.
 
-opts.dr = 0 remaps in a pass of its own after the elementwise kernel, staging
-chunks of the stream in LDS and writing each chunk in destination order;
+opts.dr = 0 remaps in a pass of its own after the elementwise kernel, writing
+the records of each chunk of the stream in destination order;
 opts.dr = 1 stores every record at its next position from inside the
 elementwise kernel.  Both must leave the same next-mode stream, bit for bit
 (integer work), and the MTTKRP outputs must be bit-identical (the elementwise
 kernel reads the same stream in the same order).  Cases cover every record
 width (16, 32, 48 bytes, i.e. chunks of 4096, 2048, 1024 records), a partial
 last chunk, an exact multiple of the chunk, one nonzero, no nonzeros, both
-planners, and the gradient's residual stream, which is remapped the same way.
+planners, the gradient's residual stream, which is remapped the same way, and
+spt_remap_for_mode over one hop (the same pass) and two hops (a scatter).
 """
 import sys
 
@@ -82,18 +83,25 @@ def test_staged_remap_empty_tensor_and_remap_for_mode():
         assert torch.count_nonzero(out).item() == 0
     assert S.tensor_info(t)["cur_mode"] == 0
     t.free()
-    # remap_for_mode (the chained remap kernel) after staged passes
+    # remap_for_mode: one hop (the chunk-ordered pass), then two hops (the
+    # chained scatter), each checked against the remap ids
     dims = (300, 200, 500)
     idx, val = synth.random_coo(dims, 20_000, seed=9, dist="zipf")
     t = S.tensor_load_coo(dims, idx, val)
+
+    def check(mode):
+        ridx, rval, cur = S.tensor_get_records(t)
+        b = S.tensor_get_remap(t, mode)
+        assert cur == mode
+        assert np.array_equal(ridx[:, b], idx) and np.array_equal(rval[b].view(np.uint32), val.view(np.uint32))
+    S.remap_for_mode(t, 1)
+    check(1)
     Y = [torch.from_numpy(y).cuda() for y in synth.random_factors(dims, 8, seed=2)]
-    out = torch.empty((dims[0], 8), device="cuda")
-    S.mttkrp(t, 0, Y, out, flags=S.FUSE_REMAP_NEXT)
-    S.remap_for_mode(t, 0)
-    ridx, rval, cur = S.tensor_get_records(t)
-    b = S.tensor_get_remap(t, 0)
-    assert cur == 0
-    assert np.array_equal(ridx[:, b], idx) and np.array_equal(rval[b].view(np.uint32), val.view(np.uint32))
+    out = torch.empty((dims[1], 8), device="cuda")
+    S.mttkrp(t, 1, Y, out, flags=S.FUSE_REMAP_NEXT)
+    check(2)
+    S.remap_for_mode(t, 1)
+    check(1)
     t.free()
 
 
