@@ -388,12 +388,13 @@ def main() -> int:
         fused = {"ms_per_pass": round(wall_f, 4), "ec_remap_kernel_ms": [round(x, 4) for x in ec_f]}
         log(f"fused remap: {wall_f:.3f} ms per all-mode pass; EC+remap kernel {['%.3f' % x for x in ec_f]} ms")
 
-    # the remap alone (Alg. 3 as a separate scatter kernel), N hops per pass
+    # the remap alone (spt_remap_for_mode, one hop per call: the remap pass
+    # without the elementwise kernel), N hops per pass
     def remap_pass():
         for d in range(N):
             S.remap_for_mode(t, (d + 1) % N)
     wall_r, _ = timed_passes(torch, S, t, K, W, remap_pass)
-    log(f"remap alone: {wall_r:.3f} ms per pass of {N} scatters")
+    log(f"remap alone: {wall_r:.3f} ms per pass of {N} one-hop remaps")
 
     rec = info["record_bytes"]
     bytes_ec = [algorithmic_bytes(dims, spec.nnz, R, rec, d, False) for d in range(N)]
