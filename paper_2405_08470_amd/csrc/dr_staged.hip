@@ -8,8 +8,8 @@
 // consecutive threads take consecutive table slots, so records of one chunk
 // that land next to each other in the next mode's stream go out in the same
 // store instruction and share memory transactions.  Each chunk (64 KB of
-// records) is read in that order too; its lines are fetched once and then hit
-// in L2.  The next mode's stream is the same as the fused form's, bit for bit.
+// records) is read in that order too; all workgroups of a chunk run on one XCD,
+// so its lines are fetched once into that XCD's L2 and then hit there.  The next mode's stream is the same as the fused form's, bit for bit.
 //
 // Tables (built once at load, per mode d, from the next positions nxt_d):
 //   ddst[c*C + j] = j-th smallest destination among the records of chunk c
@@ -39,6 +39,13 @@
 #endif
 #ifndef SPT_STAGE_THREADS
 #define SPT_STAGE_THREADS 256
+#endif
+// SPT_STAGE_XCD (form 0 only): 1 = all workgroups of a chunk on one XCD,
+// consecutive chunks on consecutive XCDs (workgroups are dealt to the 8 XCDs
+// round-robin by id, each XCD with its own L2, so a chunk's lines are fetched
+// into one L2 only); 0 = workgroups in slot order
+#ifndef SPT_STAGE_XCD
+#define SPT_STAGE_XCD 1
 #endif
 
 namespace spt {
@@ -97,7 +104,16 @@ __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_
                                                                     const uint16_t* __restrict__ doff,
                                                                     int64_t nnz) {
     constexpr int Q = RW / 4;
+#if SPT_STAGE_XCD
+    // the grid is a multiple of 8 chunks; block b runs on XCD b % 8 and takes
+    // the (b / 8)-th block of that XCD's chunks c = x, x + 8, x + 16, ...
+    constexpr unsigned BPC = C / kRemapThreads;  // workgroups per chunk
+    const unsigned b = blockIdx.x, x = b % 8u, r = b / 8u;
+    const unsigned v = ((r / BPC) * 8u + x) * BPC + r % BPC;
+    const int64_t j = (int64_t)v * kRemapThreads + threadIdx.x;
+#else
     const int64_t j = (int64_t)blockIdx.x * kRemapThreads + threadIdx.x;
+#endif
     if (j >= nnz) return;
     const int64_t p = (j / C) * C + doff[j];
     const int64_t q = ddst[j];
@@ -182,7 +198,12 @@ void launch_remap_staged(int words, int64_t nnz, const uint32_t* in, uint32_t* o
     if (nnz == 0) return;
     const int C = stage_chunk(words);
 #if SPT_STAGE_FORM == 0
+#if SPT_STAGE_XCD
+    const int64_t nchunks = (nnz + C - 1) / C;
+    const unsigned fblocks = (unsigned)(((nchunks + 7) / 8) * 8 * (C / kRemapThreads));
+#else
     const unsigned fblocks = (unsigned)((nnz + kRemapThreads - 1) / kRemapThreads);
+#endif
     if (words == 4)
         hipLaunchKernelGGL((remap_flat_kernel<4, kChunk16>), dim3(fblocks), dim3(kRemapThreads), 0, s, in, out,
                            ddst, doff, nnz);
