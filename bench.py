@@ -264,14 +264,21 @@ def phase_gradient(torch, S, synth, K, W):
 def ablation(torch, S, dims, idx, val, fac, outs, K, W, name):
     """The all-mode pass across partition counts kappa (the analog of the
     paper's threadblock-count sweep), with the remap fused into the
-    elementwise kernel instead of staged, and with the heavy-row split off
-    (pure Alg. 1): ms per pass, per-mode kernel times, largest partition."""
+    elementwise kernel instead of staged, with the heavy-row split off (pure
+    Alg. 1), and, for four modes or more, with each record layout: ms per
+    pass, per-mode kernel times, largest partition."""
     N = len(dims)
     rows = []
-    settings = [(k, None, "staged") for k in (2048, 4096, 8192, 16384, 32768, 65536)]
-    settings += [(8192, None, "fused"), (8192, 0, "staged")]
-    for kappa, cap, remap in settings:
-        t = S.tensor_load_coo(dims, idx, val, kappa=kappa, split_cap=cap, prep="device", remap=remap)
+    settings = [(k, None, "staged", "auto") for k in (2048, 4096, 8192, 16384, 32768, 65536)]
+    settings += [(8192, None, "fused", "auto"), (8192, 0, "staged", "auto")]
+    if N >= 4:
+        # the record layouts (Sec. 3.5) with a kernel for this shape
+        small = max(dims) <= 65536
+        lays = (["half16"] if small and N != 7 else []) + (["packed"] if N <= 6 else []) + ["word32"]
+        settings += [(8192, None, "staged", lay) for lay in lays]
+    for kappa, cap, remap, layout in settings:
+        t = S.tensor_load_coo(dims, idx, val, kappa=kappa, split_cap=cap, prep="device", remap=remap,
+                              layout=layout)
         info = S.tensor_info(t)
 
         def run(tt=t):
@@ -281,7 +288,8 @@ def ablation(torch, S, dims, idx, val, fac, outs, K, W, name):
         wall, tm = timed_passes(torch, S, t, kk, ww, run)
         ec, rm = per_call(tm, "ec_ms", N), per_call(tm, "remap_ms", N)
         t.free()
-        row = {"kappa": kappa, "split": cap is None, "remap": remap, "ms_per_pass": round(wall, 4),
+        row = {"kappa": kappa, "split": cap is None, "remap": remap, "layout": layout,
+               "record_bytes": info["record_bytes"], "ms_per_pass": round(wall, 4),
                "ec_kernel_ms": [round(x, 4) for x in ec], "remap_kernel_ms": [round(x, 4) for x in rm],
                "max_partition": info["max_load"], "mean_partition": round(len(val) / kappa, 1)}
         log(f"ablation {row}")

@@ -71,7 +71,18 @@ typedef struct spt_opts {
                            tables, 6 bytes per nonzero and mode.  1 = fused: the elementwise kernel stores
                            every record at its next position.  The next
                            stream is identical either way                   */
-    int32_t reserved[2];/* must be zero                                      */
+    int32_t layout;     /* record layout of the stream (Sec. 3.5): 0 = chosen
+                           by the library (32-bit indices for N <= 3; 16-bit
+                           fields when every mode has <= 65536 rows; else
+                           bit fields of ceil(log2 I_w) bits; else wider
+                           records); 1 = 32-bit indices (16 / 32 / 48-byte
+                           records for N <= 3 / <= 7 / 8); 2 = 16-bit fields
+                           (N = 4..6: 16 B, N = 8: 32 B; every mode
+                           <= 65536 rows); 3 = packed bit fields (N = 4..6,
+                           at most 96 index bits: 16 B).  A layout that does
+                           not fit fails with SPT_ERR_UNSUPPORTED.  Results
+                           are identical for every layout                   */
+    int32_t reserved;   /* must be zero                                      */
 } spt_opts;
 
 /* Summary of a loaded tensor (spt_tensor_info). */

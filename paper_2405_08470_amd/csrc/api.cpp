@@ -144,10 +144,11 @@ spt_status get_opts(const spt_opts* o, PlanOptions* po, int* copies, int* dr) {
     *copies = 0;
     *dr = 0;
     if (!o) return SPT_OK;
-    for (int k = 0; k < 2; ++k)
-        if (o->reserved[k] != 0) return fail(SPT_ERR_INVALID_ARG, "opts.reserved must be zero");
+    if (o->reserved != 0) return fail(SPT_ERR_INVALID_ARG, "opts.reserved must be zero");
     if (o->dr != 0 && o->dr != 1) return fail(SPT_ERR_INVALID_ARG, "opts.dr must be 0 or 1");
     *dr = o->dr;
+    if (o->layout < 0 || o->layout > 3) return fail(SPT_ERR_INVALID_ARG, "opts.layout must be 0..3");
+    po->layout = o->layout;
     if (o->prep != 0 && o->prep != 1) return fail(SPT_ERR_INVALID_ARG, "opts.prep must be 0 or 1");
     po->prep = o->prep;
     if (o->kappa < 0) return fail(SPT_ERR_INVALID_ARG, "opts.kappa must be >= 0");
@@ -409,9 +410,10 @@ spt_status load_device(int32_t nmodes, const int64_t* dims, int64_t nnz, const i
         t->nnz = nnz;
         for (int w = 0; w < nmodes; ++w) t->dims[w] = dims[w];
         t->copies = copies;
-        if (!spt::choose_layout(nmodes, dims, &t->lay)) {
+        if (!spt::choose_layout(nmodes, dims, po.layout, &t->lay)) {
             delete t;
-            return fail(SPT_ERR_UNSUPPORTED, "index bits exceed a 32-byte record");
+            return fail(SPT_ERR_UNSUPPORTED, "the record layout asked for in opts.layout has no kernel for "
+                                             "this mode count and these mode sizes");
         }
         spt::DevicePlan dp;
         std::string msg;
@@ -516,9 +518,10 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
         t->nnz = nnz;
         for (int w = 0; w < nmodes; ++w) t->dims[w] = dims[w];
         t->copies = copies;
-        if (!spt::choose_layout(nmodes, dims, &t->lay)) {
+        if (!spt::choose_layout(nmodes, dims, po.layout, &t->lay)) {
             delete t;
-            return fail(SPT_ERR_UNSUPPORTED, "index bits exceed a 32-byte record");
+            return fail(SPT_ERR_UNSUPPORTED, "the record layout asked for in opts.layout has no kernel for "
+                                             "this mode count and these mode sizes");
         }
         Plan plan;
         spt::build_plan(nmodes, dims, nnz, indices, values, po, &plan);

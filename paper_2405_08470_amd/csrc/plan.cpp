@@ -281,7 +281,7 @@ std::string validate_shape(int nmodes, const int64_t* dims, int64_t nnz, const i
     return "";
 }
 
-bool choose_layout(int nmodes, const int64_t* dims, RecordLayout* lay) {
+bool choose_layout(int nmodes, const int64_t* dims, int pref, RecordLayout* lay) {
     lay->nmodes = nmodes;
     int packed_bits = 0;
     bool small = true;
@@ -301,6 +301,24 @@ bool choose_layout(int nmodes, const int64_t* dims, RecordLayout* lay) {
             o += b;
         }
     };
+    if (nmodes < 1 || nmodes > kMaxModes) return false;
+    const int word32_words = nmodes <= 3 ? 4 : nmodes <= 7 ? 8 : 12;
+    switch (pref) {
+        case kLayoutWord32:
+            set(kWord32, word32_words);
+            return true;
+        case kLayoutHalf16:
+            // 16-bit fields exist for 4..6 modes (16 B) and 8 modes (32 B)
+            if (!small || nmodes <= 3 || nmodes == 7) return false;
+            set(kHalf16, nmodes <= 6 ? 4 : 8);
+            return true;
+        case kLayoutPacked:
+            if (nmodes <= 3 || nmodes > 6 || packed_bits > 96) return false;
+            set(kPacked, 4);
+            return true;
+        default:
+            break;
+    }
     if (nmodes <= 3)
         set(kWord32, 4);
     else if (small && nmodes <= 6)
@@ -313,7 +331,7 @@ bool choose_layout(int nmodes, const int64_t* dims, RecordLayout* lay) {
         set(kHalf16, 8);
     else
         set(kWord32, 12);
-    return nmodes >= 1 && nmodes <= kMaxModes;
+    return true;
 }
 
 void pack_record(const RecordLayout& lay, const int32_t* idx, int64_t nnz, const float* val,

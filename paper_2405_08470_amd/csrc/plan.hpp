@@ -63,6 +63,7 @@ struct PlanOptions {
     bool remap_ids = true;   // build orders / remap ids
     bool norm = true;        // compute ||X||^2 of the coalesced tensor
     int prep = 0;            // 0: host planner, 1: device planner (load only)
+    int layout = 0;          // kLayout* record layout preference (load only)
 };
 
 // Items of one mode after Alg. 1: rows, or pieces of rows heavier than the
@@ -103,7 +104,10 @@ void build_plan(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx
 
 // Chooses the smallest record, preferring layouts the kernels decode with
 // fixed shifts; returns false if no layout fits.
-bool choose_layout(int nmodes, const int64_t* dims, RecordLayout* lay);
+// Record layout preference (spt_opts.layout): automatic, or one kind forced.
+enum { kLayoutAuto = 0, kLayoutWord32 = 1, kLayoutHalf16 = 2, kLayoutPacked = 3 };
+// false if the preferred kind has no kernel for this mode count or these dims
+bool choose_layout(int nmodes, const int64_t* dims, int pref, RecordLayout* lay);
 
 // Packs nonzero e into `words` 32-bit words.
 void pack_record(const RecordLayout& lay, const int32_t* idx, int64_t nnz, const float* val,

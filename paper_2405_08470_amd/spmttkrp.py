@@ -38,7 +38,7 @@ class SptError(RuntimeError):
 class spt_opts(ctypes.Structure):
     _fields_ = [("kappa", ctypes.c_int32), ("copies", ctypes.c_int32),
                 ("split_cap", ctypes.c_int64), ("prep", ctypes.c_int32),
-                ("dr", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("dr", ctypes.c_int32), ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class spt_info(ctypes.Structure):
@@ -106,8 +106,11 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(stream))
 
 
+LAYOUTS = {"auto": 0, "word32": 1, "half16": 2, "packed": 3}
+
+
 def _opts(kappa: int, split_cap: Optional[int], copies: int, prep: str = "host",
-          remap: str = "staged") -> spt_opts:
+          remap: str = "staged", layout: str = "auto") -> spt_opts:
     o = spt_opts()
     o.kappa = int(kappa)
     o.copies = int(copies)
@@ -117,6 +120,9 @@ def _opts(kappa: int, split_cap: Optional[int], copies: int, prep: str = "host",
     if remap not in ("staged", "fused"):
         raise ValueError("remap must be 'staged' or 'fused'")
     o.dr = 0 if remap == "staged" else 1
+    if layout not in LAYOUTS:
+        raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+    o.layout = LAYOUTS[layout]
     # split_cap: None -> default ceil(nnz/kappa); <= 0 -> never split
     o.split_cap = 0 if split_cap is None else (int(split_cap) if split_cap > 0 else -1)
     return o
@@ -163,13 +169,15 @@ class Tensor:
 
 
 def tensor_load_coo(dims, indices, values, kappa: int = 0, split_cap: Optional[int] = None,
-                    copies: int = 0, stream=None, prep: str = "host", remap: str = "staged") -> Tensor:
+                    copies: int = 0, stream=None, prep: str = "host", remap: str = "staged",
+                    layout: str = "auto") -> Tensor:
     """prep: "host" (planner threads) or "device" (planner kernels).
     remap: "staged" (a remap pass after the elementwise kernel) or "fused"
-    (the elementwise kernel stores each record at its next position)."""
+    (the elementwise kernel stores each record at its next position).
+    layout: "auto", "word32", "half16" or "packed" (record layout)."""
     dims64, idx, val = _host_coo(dims, indices, values)
     out = ctypes.c_void_p()
-    o = _opts(kappa, split_cap, copies, prep, remap)
+    o = _opts(kappa, split_cap, copies, prep, remap, layout)
     _check(lib().spt_tensor_load_coo(len(dims64), dims64.ctypes.data, idx.shape[1], idx.ctypes.data,
                                      val.ctypes.data, ctypes.byref(o), _stream(stream),
                                      ctypes.byref(out)))

@@ -83,6 +83,8 @@ def test_planner_rejects_bad_input(dims, idx, name):
     ("dr", -1, "opts.dr must be 0 or 1"),
     ("prep", 2, "opts.prep must be 0 or 1"),
     ("copies", 3, "opts.copies must be 0 or 1"),
+    ("layout", 4, "opts.layout must be 0..3"),
+    ("layout", -1, "opts.layout must be 0..3"),
 ])
 def test_options_are_validated_before_any_device_work(field, value, msg):
     import ctypes
@@ -100,7 +102,7 @@ def test_options_are_validated_before_any_device_work(field, value, msg):
 def test_options_reserved_words_must_be_zero_and_remap_forms_map():
     import ctypes
     o = S._opts(0, None, 0)
-    o.reserved[1] = 1
+    o.reserved = 1
     dims = np.array([4, 3, 2], dtype=np.int64)
     idx = np.zeros((3, 1), dtype=np.int32)
     k = ctypes.c_int32()
@@ -111,4 +113,7 @@ def test_options_reserved_words_must_be_zero_and_remap_forms_map():
     assert S._opts(0, None, 0, remap="fused").dr == 1
     with pytest.raises(ValueError):
         S._opts(0, None, 0, remap="pull")
+    assert [S._opts(0, None, 0, layout=k).layout for k in ("auto", "word32", "half16", "packed")] == [0, 1, 2, 3]
+    with pytest.raises(ValueError):
+        S._opts(0, None, 0, layout="soa")
     assert [S.stage_chunk(b) for b in (16, 32, 48)] == [4096, 2048, 1024]
