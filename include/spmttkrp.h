@@ -169,7 +169,11 @@ spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void *const *factors,
  *   lambda   device double[rank], receives the column norms of the last mode
  *   fit      host double*, receives 1 - ||X - Xhat|| / ||X|| (synchronises
  *            the stream); NULL to skip
- * The stream must be in mode 0's order on entry and is on exit.
+ * The stream must be in mode 0's order on entry and is on exit.  With
+ * opts.dr = 0 each mode's remap pass runs on a side stream the handle owns
+ * (default priority), beside that mode's fixup and factor update; the
+ * caller's stream waits for it before the next mode, so all of the call's
+ * work is ordered on `stream` as usual.
  * Device workspace is allocated on first use per rank and kept by the
  * handle.  Errors: STATE, UNSUPPORTED, NOT_SPD (reported by the call that
  * synchronises: this one when fit != NULL, else the next), HIP, OOM.

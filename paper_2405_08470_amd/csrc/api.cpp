@@ -15,6 +15,12 @@
 #include "device_plan.hpp"
 #include "plan.hpp"
 
+// CP-ALS runs each mode's remap pass on a side stream, beside the mode's
+// fixup and dense update (0: everything on the caller's stream)
+#ifndef SPT_ALS_SIDE_REMAP
+#define SPT_ALS_SIDE_REMAP 1
+#endif
+
 using spt::Plan;
 using spt::PlanOptions;
 using spt::RecordLayout;
@@ -93,12 +99,18 @@ struct spt_tensor_s {
     int32_t* status = nullptr;
     int32_t* status_host = nullptr;
     hipEvent_t status_event = nullptr;
+    // CP-ALS: the remap pass of a mode on a side stream, beside that mode's
+    // fixup and dense update (joined before the next mode's EC)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool join_pending = false;
     bool status_pending = false;
     std::vector<void*> ws_allocs;
     // kernel timing
     struct Timed {
         int mode;
         hipEvent_t ev[5];  // before EC, after EC, after staged remap, after fixup, after ALS step
+        bool side;         // the remap ran on the side stream (ev[2] recorded there)
     };
     bool timing = false;
     std::vector<Timed> timed;
@@ -136,6 +148,11 @@ void release(spt_tensor_s* t) {
     for (void* p : t->ws_allocs) (void)hipFree(p);
     if (t->status_host) (void)hipHostFree(t->status_host);
     if (t->status_event) (void)hipEventDestroy(t->status_event);
+    if (t->side) (void)hipStreamDestroy(t->side);
+    if (t->ev_fork) (void)hipEventDestroy(t->ev_fork);
+    if (t->ev_join) (void)hipEventDestroy(t->ev_join);
+    t->side = nullptr;
+    t->ev_fork = t->ev_join = nullptr;
     t->allocs.clear();
     t->ws_allocs.clear();
 }
@@ -206,11 +223,31 @@ hipEvent_t mark(spt_tensor_s* t, hipStream_t s) {
     return e;
 }
 
+spt_status ensure_side(spt_tensor_s* t) {
+    if (t->side) return SPT_OK;
+    HIPCHK(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));  // default priority
+    HIPCHK(hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming));
+    return SPT_OK;
+}
+
+// s waits for the side stream's last remap pass
+spt_status join_side(spt_tensor_s* t, hipStream_t s) {
+    if (!t->join_pending) return SPT_OK;
+    HIPCHK(hipStreamWaitEvent(s, t->ev_join, 0));
+    t->join_pending = false;
+    return SPT_OK;
+}
+
 // EC (+ remap into rec_out when it is not null) and fixup for one mode over
-// the stream rec_in, which must be in that mode's order.
+// the stream rec_in, which must be in that mode's order.  With side_remap the
+// remap pass runs on the tensor's side stream after EC, and the caller must
+// call join_side() before anything on s reads rec_out.
 spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32_t* rec_out,
-                       const void* const* factors, int fdtype, int rank, float* out, hipStream_t s) {
-    spt_status st = ensure_carry(t, rank);
+                       const void* const* factors, int fdtype, int rank, float* out, hipStream_t s,
+                       bool side_remap = false) {
+    spt_status st = join_side(t, s);
+    if (st == SPT_OK) st = ensure_carry(t, rank);
     if (st != SPT_OK) return st;
     const int N = t->N;
     // the staged pass remaps after EC when its tables exist, else EC stores
@@ -234,13 +271,24 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
         a.foff[k] = t->lay.off[k];
         a.fmask[k] = (uint32_t)((uint64_t(1) << t->lay.bits[k]) - 1);
     }
-    spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr, nullptr}};
+    spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr, nullptr}, false};
     tm.ev[0] = mark(t, s);
     if (!spt::launch_ec(N, rank, fdtype, t->lay.words, t->lay.kind, t->kappa, a, s))
         return fail(SPT_ERR_UNSUPPORTED, "no kernel compiled for this mode count / rank / record size");
     HIPCHK(hipGetLastError());
     tm.ev[1] = mark(t, s);
-    if (staged) {
+    if (staged && side_remap) {
+        spt_status st2 = ensure_side(t);
+        if (st2 != SPT_OK) return st2;
+        HIPCHK(hipEventRecord(t->ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(t->side, t->ev_fork, 0));
+        spt::launch_remap_staged(t->lay.words, t->nnz, rec_in, rec_out, t->ddst[mode], t->doff[mode], t->side);
+        HIPCHK(hipGetLastError());
+        tm.ev[2] = mark(t, t->side);
+        tm.side = true;
+        HIPCHK(hipEventRecord(t->ev_join, t->side));
+        t->join_pending = true;
+    } else if (staged) {
         spt::launch_remap_staged(t->lay.words, t->nnz, rec_in, rec_out, t->ddst[mode], t->doff[mode], s);
         HIPCHK(hipGetLastError());
         tm.ev[2] = mark(t, s);
@@ -264,11 +312,11 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
 
 // mode d's stream and, when remapping, the target buffer of the tensor
 spt_status run_mttkrp(spt_tensor_s* t, int mode, const void* const* factors, int fdtype, int rank,
-                      float* out, bool fuse, hipStream_t s) {
+                      float* out, bool fuse, hipStream_t s, bool side_remap = false) {
     if (t->copies)
         return launch_mode(t, mode, t->rec_mode[mode], nullptr, factors, fdtype, rank, out, s);
     spt_status st = launch_mode(t, mode, t->rec[t->cur], fuse ? t->rec[1 - t->cur] : nullptr,
-                                factors, fdtype, rank, out, s);
+                                factors, fdtype, rank, out, s, side_remap);
     if (st != SPT_OK) return st;
     if (fuse) {
         t->cur = 1 - t->cur;
@@ -298,6 +346,8 @@ spt_status launch_forward_pass(spt_tensor_s* t, const uint32_t* rec_in, uint32_t
 }
 
 spt_status do_remap(spt_tensor_s* t, int mode, hipStream_t s) {
+    spt_status st = join_side(t, s);
+    if (st != SPT_OK) return st;
     if (t->copies) {
         t->cur_mode = mode;
         return SPT_OK;
@@ -455,6 +505,10 @@ spt_status load_device(int32_t nmodes, const int64_t* dims, int64_t nnz, const i
         if (st == SPT_OK && !copies) {
             t->rec[0] = dp.rec0;
             st = dalloc(t, &t->rec[1], (size_t)std::max<int64_t>(1, nnz) * t->lay.words, &t->allocs);
+            // the remap target holds defined records (index 0) until the first remap
+            if (st == SPT_OK && hipMemsetAsync(t->rec[1], 0, sizeof(uint32_t) * std::max<int64_t>(1, nnz) * t->lay.words,
+                                               s) != hipSuccess)
+                st = fail(SPT_ERR_HIP, "hipMemsetAsync of the remap target");
         }
         // the uploads read the plan's host vectors
         if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess)
@@ -587,6 +641,10 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
             pack_stream(plan.mode[0].order, recs);
             if ((st = upload(t, &t->rec[0], recs, s)) == SPT_OK)
                 st = dalloc(t, &t->rec[1], recs.size(), &t->allocs);
+            // the remap target holds defined records (index 0) until the first remap
+            if (st == SPT_OK && !recs.empty() &&
+                hipMemsetAsync(t->rec[1], 0, sizeof(uint32_t) * recs.size(), s) != hipSuccess)
+                st = fail(SPT_ERR_HIP, "hipMemsetAsync of the remap target");
         }
         if (st == SPT_OK && hipStreamSynchronize(s) != hipSuccess)
             st = fail(SPT_ERR_HIP, "hipStreamSynchronize after upload");
@@ -623,10 +681,12 @@ spt_status spt_timing_control(spt_tensor_t t, int32_t enable, spt_timing* out) {
         std::memset(out, 0, sizeof(*out));
         for (const auto& tm : t->timed) {
             HIPCHK(hipEventSynchronize(tm.ev[4] ? tm.ev[4] : tm.ev[3]));
+            HIPCHK(hipEventSynchronize(tm.ev[2]));
             float a = 0.f, r = 0.f, b = 0.f, c = 0.f;
             HIPCHK(hipEventElapsedTime(&a, tm.ev[0], tm.ev[1]));
             if (tm.ev[2] != tm.ev[1]) HIPCHK(hipEventElapsedTime(&r, tm.ev[1], tm.ev[2]));
-            HIPCHK(hipEventElapsedTime(&b, tm.ev[2], tm.ev[3]));
+            // a side-stream remap overlaps the fixup: time the fixup from EC's end
+            HIPCHK(hipEventElapsedTime(&b, tm.side ? tm.ev[1] : tm.ev[2], tm.ev[3]));
             if (tm.ev[4]) HIPCHK(hipEventElapsedTime(&c, tm.ev[3], tm.ev[4]));
             out->calls[tm.mode] += 1;
             out->ec_ms[tm.mode] += a;
@@ -744,7 +804,8 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
         if (bf16) spt::launch_to_bf16((const float*)factors[w], t->shadow[w], t->dims[w] * rank, s);
     }
     for (int d = 0; d < N; ++d) {
-        st = run_mttkrp(t, d, gath, fdtype, rank, t->M, true, s);
+        // the remap pass of mode d overlaps its fixup and dense update
+        st = run_mttkrp(t, d, gath, fdtype, rank, t->M, true, s, SPT_ALS_SIDE_REMAP != 0);
         if (st != SPT_OK) return st;
         spt::launch_normal_inverse(rank, N, d, t->grams, t->Vinv, t->status, s);
         const int nb = spt::solve_blocks(t->dims[d]);
@@ -759,6 +820,7 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
         HIPCHK(hipGetLastError());
         if (t->timing && !t->timed.empty() && t->timed.back().mode == d && !t->timed.back().ev[4])
             t->timed.back().ev[4] = mark(t, s);
+        if ((st = join_side(t, s)) != SPT_OK) return st;
     }
     if (t->copies) t->cur_mode = 0;
     HIPCHK(hipMemcpyAsync(t->status_host, t->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
