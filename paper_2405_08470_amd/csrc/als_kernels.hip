@@ -8,9 +8,14 @@
 #include "kernels.hpp"
 
 // Y = M V^-1 on the FP64 matrix cores (1) or with V^-1 in LDS (0); the
-// matrix-core form waits for a check of the instruction's lane layout.
+// instruction's lane layout used below was measured on the device.
 #ifndef SPT_SOLVE_MFMA
 #define SPT_SOLVE_MFMA 1
+#endif
+// Grams of the caller's factors at the start of a sweep on the FP64 matrix
+// cores (rank 8: the LDS kernel)
+#ifndef SPT_GRAM_MFMA
+#define SPT_GRAM_MFMA 1
 #endif
 
 namespace spt {
@@ -385,6 +390,66 @@ __global__ __launch_bounds__(256) void solve_rows_mfma_kernel(const float* __res
     }
 }
 
+// Partial Grams Y^T Y on the FP64 matrix cores (R a multiple of 16): each
+// wave takes 16-row tiles; lane (rl = lane % 16, q = lane / 16) holds
+// Y(r0 + 4v + q, 16c + rl), which is both the A operand (column tile c0 of
+// Y^T) and the B operand (column tile c1 of Y) of v_mfma_f64_16x16x4f64 for
+// the 4 rows r0 + 4v .. r0 + 4v + 3.  The waves' tiles are summed in LDS in
+// wave order, and the block writes partial[blockIdx][R*R].
+template <int R>
+__global__ __launch_bounds__(256) void gram_mfma_kernel(const float* __restrict__ Y, int64_t rows,
+                                                         double* __restrict__ partial) {
+    static_assert(R % 16 == 0, "rank");
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    constexpr int CT = R / 16;
+    constexpr int NP = CT * (CT + 1) / 2;
+    constexpr int E = R * R;
+    __shared__ double gsh[E];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rl = lane & 15, q = lane >> 4;
+    v4d gacc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) gacc[p] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t tiles = (rows + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t r0 = tile * 16;
+        double yd[CT][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = r0 + 4 * v + q;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) yd[ct][v] = row < rows ? (double)Y[row * R + 16 * ct + rl] : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int p = 0;
+#pragma unroll
+            for (int c0 = 0; c0 < CT; ++c0)
+#pragma unroll
+                for (int c1 = c0; c1 < CT; ++c1, ++p)
+                    gacc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(yd[c0][v], yd[c1][v], gacc[p], 0, 0, 0);
+        }
+    }
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w) {
+            int p = 0;
+#pragma unroll
+            for (int c0 = 0; c0 < CT; ++c0)
+#pragma unroll
+                for (int c1 = c0; c1 < CT; ++c1, ++p)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * c0 + 4 * v + q, j = 16 * c1 + rl;
+                        const double x = gacc[p][v];
+                        gsh[i * R + j] = w == 0 ? x : gsh[i * R + j] + x;
+                        if (c1 != c0) gsh[j * R + i] = w == 0 ? x : gsh[j * R + i] + x;
+                    }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < E; e += 256) partial[(int64_t)blockIdx.x * E + e] = gsh[e];
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void als_finish_kernel(const double* __restrict__ Gun,
                                                           const double* __restrict__ Isum,
@@ -459,6 +524,8 @@ void by_rank(int rank, dim3 grid, dim3 block, hipStream_t s, Args... args) {
 }
 
 template <int R> struct GramP { static constexpr auto fn = gram_partial_kernel<R>; };
+template <int R> struct GramMfma { static constexpr auto fn = gram_mfma_kernel<R>; };
+template <> struct GramMfma<8> { static constexpr auto fn = gram_partial_kernel<8>; };
 template <int R> struct NormInv { static constexpr auto fn = normal_inverse_kernel<R>; };
 template <int R> struct Solve { static constexpr auto fn = solve_rows_kernel<R>; };
 template <int R> struct SolveMfma { static constexpr auto fn = solve_rows_mfma_kernel<R>; };
@@ -473,7 +540,11 @@ int gram_blocks(int64_t rows) {
 }
 
 void launch_gram_partial(int rank, const float* Y, int64_t rows, double* partial, hipStream_t s) {
+#if SPT_GRAM_MFMA
+    by_rank<GramMfma>(rank, dim3(gram_blocks(rows)), dim3(256), s, Y, rows, partial);
+#else
     by_rank<GramP>(rank, dim3(gram_blocks(rows)), dim3(256), s, Y, rows, partial);
+#endif
 }
 
 void launch_reduce_partials(const double* partial, int nblocks, int E, double* out, hipStream_t s) {
