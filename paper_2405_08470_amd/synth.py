@@ -120,7 +120,7 @@ def zipf_ranks(seed: int, sid: int, n: int, size: int, s: float) -> np.ndarray:
 
 # Stream ids: mode d indices -> d; factor w -> 16 + w; values -> 32;
 # noise -> 33; starting-point perturbation of factor w -> 40 + w;
-# permutations of mode d -> 48 + d; top-up draws -> 64 + round.
+# permutations of mode d -> 48 + d; top-up draws -> 64 + top-up iteration.
 SID_FACTOR = 16
 SID_VALUES = 32
 SID_NOISE = 33

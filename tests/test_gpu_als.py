@@ -112,7 +112,7 @@ def test_planted_low_rank_recovery_on_gpu():
     # normal matrix singular (one ridge retry) and keep lambda = 0
     # Near fit = 1 the fit formula cancels (||X||^2 + ||Xhat||^2 - 2<X, Xhat>),
     # so FP32 MTTKRP rounding of ~1e-7 shows up as ~sqrt(1e-7) in the fit;
-    # recovery is judged on the dense FP64 residual of the returned factors.
+    # recovery is measured by the dense FP64 residual of the returned factors.
     X = oracle.full_tensor(dims, idx, val)
     best_res, best_fit = np.inf, 0.0
     for s in (8, 9, 10):
