@@ -15,12 +15,6 @@
 #include "device_plan.hpp"
 #include "plan.hpp"
 
-// CP-ALS runs each mode's remap pass on a side stream, beside the mode's
-// fixup and dense update (0: everything on the caller's stream)
-#ifndef SPT_ALS_SIDE_REMAP
-#define SPT_ALS_SIDE_REMAP 1
-#endif
-
 using spt::Plan;
 using spt::PlanOptions;
 using spt::RecordLayout;
@@ -71,7 +65,6 @@ struct spt_tensor_s {
     int32_t* split_row[8] = {};
     int32_t* split_ptr[8] = {};
     int32_t* empty_rows[8] = {};
-    int32_t* dsrc[8] = {};        // experimental destination-sorted remap only
     int dr = 0;                   // 0: staged remap pass after EC; 1: remap fused into EC
     int32_t* ddst[8] = {};        // staged remap tables of mode d -> d+1 (dr == 0)
     uint16_t* doff[8] = {};
@@ -119,8 +112,6 @@ struct spt_tensor_s {
 };
 
 namespace {
-
-[[maybe_unused]] int32_t t_kappa(const Plan& p) { return p.kappa; }
 
 template <typename T>
 spt_status dalloc(spt_tensor_s* t, T** p, size_t count, std::vector<void*>* list) {
@@ -257,7 +248,6 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
     a.rec_in = rec_in;
     a.rec_out = staged ? nullptr : rec_out;
     a.nxt = a.rec_out ? t->nxt[mode] : nullptr;
-    a.dsrc = a.rec_out ? t->dsrc[mode] : nullptr;
     a.ptr = t->ptr[mode];
     a.psplit_ptr = t->psplit_ptr[mode];
     a.psplit_row = t->psplit_row[mode];
@@ -608,27 +598,6 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
                 nxt.resize(nnz);
                 spt::next_positions(mp.order.data(), plan.mode[(d + 1) % nmodes].remap.data(), nnz,
                                     nxt.data());
-#if SPT_DR_SORTED
-                {
-                    // slots of each partition in the order of their destinations
-                    std::vector<int32_t> prv(nnz), zsrc(nnz), cur(mp.ptr.begin(), mp.ptr.end() - 1);
-                    for (int64_t p = 0; p < nnz; ++p) prv[nxt[p]] = (int32_t)p;
-                    for (int32_t z = 0; z < t_kappa(plan); ++z)
-                        for (int64_t p = mp.ptr[z]; p < mp.ptr[z + 1]; ++p) zsrc[p] = z;
-                    std::vector<int32_t> dsrc(nnz), ddst(nnz);
-                    for (int64_t o = 0; o < nnz; ++o) {
-                        const int64_t q = cur[zsrc[prv[o]]]++;
-                        dsrc[q] = prv[o];
-                        ddst[q] = (int32_t)o;
-                    }
-                    nxt.swap(ddst);
-                    if ((st = upload(t, &t->dsrc[d], dsrc, s)) != SPT_OK) break;
-                    if (hipStreamSynchronize(s) != hipSuccess) {
-                        st = fail(SPT_ERR_HIP, "hipStreamSynchronize after upload");
-                        break;
-                    }
-                }
-#endif
                 if ((st = upload(t, &t->nxt[d], nxt, s)) != SPT_OK) break;
             }
             // the uploads above read host vectors that are reused next mode
@@ -805,7 +774,7 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
     }
     for (int d = 0; d < N; ++d) {
         // the remap pass of mode d overlaps its fixup and dense update
-        st = run_mttkrp(t, d, gath, fdtype, rank, t->M, true, s, SPT_ALS_SIDE_REMAP != 0);
+        st = run_mttkrp(t, d, gath, fdtype, rank, t->M, true, s, true);
         if (st != SPT_OK) return st;
         spt::launch_normal_inverse(rank, N, d, t->grams, t->Vinv, t->status, s);
         const int nb = spt::solve_blocks(t->dims[d]);

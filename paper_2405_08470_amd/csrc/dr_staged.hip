@@ -23,39 +23,19 @@
 
 #include "kernels.hpp"
 
-// Build options (measurement only; the defaults are the measured best):
-//   SPT_STAGE_CHUNK16   records per chunk for 16-byte records (32-byte: half,
-//                       48-byte: a quarter); a power of two
-//   SPT_STAGE_FORM      0: one record per thread over the whole grid, read
-//                       from L2; 1: one workgroup per chunk, staged in LDS
-//                       with coalesced reads; 2: one workgroup per chunk,
-//                       read from L2
-//   SPT_STAGE_THREADS   threads per workgroup of the remap pass
+// Records per chunk for 16-byte records (32-byte: half, 48-byte: a quarter);
+// a power of two.
 #ifndef SPT_STAGE_CHUNK16
 #define SPT_STAGE_CHUNK16 4096
-#endif
-#ifndef SPT_STAGE_FORM
-#define SPT_STAGE_FORM 0
-#endif
-#ifndef SPT_STAGE_THREADS
-#define SPT_STAGE_THREADS 256
-#endif
-// SPT_STAGE_XCD (form 0 only): 1 = all workgroups of a chunk on one XCD,
-// consecutive chunks on consecutive XCDs (workgroups are dealt to the 8 XCDs
-// round-robin by id, each XCD with its own L2, so a chunk's lines are fetched
-// into one L2 only); 0 = workgroups in slot order
-#ifndef SPT_STAGE_XCD
-#define SPT_STAGE_XCD 1
 #endif
 
 namespace spt {
 namespace {
 
 constexpr int kStageThreads = 256;  // table sort
-constexpr int kRemapThreads = SPT_STAGE_THREADS;
+constexpr int kRemapThreads = 256;
 constexpr int kChunk16 = SPT_STAGE_CHUNK16;
 static_assert((kChunk16 & (kChunk16 - 1)) == 0 && kChunk16 >= 1024 && kChunk16 <= 16384, "chunk");
-static_assert(SPT_STAGE_FORM != 1 || kChunk16 <= 4096, "a staged chunk must fit 64 KB of LDS");
 
 // One workgroup per chunk: bitonic sort of (destination, offset) pairs in LDS.
 template <int C>
@@ -104,16 +84,12 @@ __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_
                                                                     const uint16_t* __restrict__ doff,
                                                                     int64_t nnz) {
     constexpr int Q = RW / 4;
-#if SPT_STAGE_XCD
     // the grid is a multiple of 8 chunks; block b runs on XCD b % 8 and takes
     // the (b / 8)-th block of that XCD's chunks c = x, x + 8, x + 16, ...
     constexpr unsigned BPC = C / kRemapThreads;  // workgroups per chunk
     const unsigned b = blockIdx.x, x = b % 8u, r = b / 8u;
     const unsigned v = ((r / BPC) * 8u + x) * BPC + r % BPC;
     const int64_t j = (int64_t)v * kRemapThreads + threadIdx.x;
-#else
-    const int64_t j = (int64_t)blockIdx.x * kRemapThreads + threadIdx.x;
-#endif
     if (j >= nnz) return;
     const int64_t p = (j / C) * C + doff[j];
     const int64_t q = ddst[j];
@@ -121,53 +97,6 @@ __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_
     uint4* dst = reinterpret_cast<uint4*>(out);
 #pragma unroll
     for (int w = 0; w < Q; ++w) dst[q * Q + w] = src[p * Q + w];
-}
-
-// One workgroup per chunk of C records of RW 32-bit words.
-template <int RW, int C>
-__global__ __launch_bounds__(kRemapThreads) void remap_staged_kernel(const uint32_t* __restrict__ in,
-                                                                      uint32_t* __restrict__ out,
-                                                                      const int32_t* __restrict__ ddst,
-                                                                      const uint16_t* __restrict__ doff,
-                                                                      int64_t nnz) {
-    constexpr int Q = RW / 4;  // 16-byte words per record
-    const int64_t base = (int64_t)blockIdx.x * C;
-    const int cnt = (int)((nnz - base) < C ? (nnz - base) : C);
-    const uint4* src = reinterpret_cast<const uint4*>(in) + base * Q;
-#if SPT_STAGE_FORM == 1
-    constexpr int PER = C * Q / kRemapThreads;
-    __shared__ uint4 buf[C * Q];
-    if (cnt == C) {
-        uint4 v[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) v[k] = src[k * kRemapThreads + threadIdx.x];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) buf[k * kRemapThreads + threadIdx.x] = v[k];
-    } else {
-        for (int i = threadIdx.x; i < cnt * Q; i += kRemapThreads) buf[i] = src[i];
-    }
-    __syncthreads();
-#else
-    const uint4* buf = src;  // the chunk is read in destination order; its lines stay in L2
-#endif
-    uint4* dst = reinterpret_cast<uint4*>(out);
-    constexpr int U = 4;
-    for (int j0 = 0; j0 < cnt; j0 += U * kRemapThreads) {
-        int32_t q[U];
-        int o[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = j0 + u * kRemapThreads + (int)threadIdx.x;
-            q[u] = j < cnt ? ddst[base + j] : -1;
-            o[u] = j < cnt ? (int)doff[base + j] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (q[u] < 0) continue;
-#pragma unroll
-            for (int w = 0; w < Q; ++w) dst[(int64_t)q[u] * Q + w] = buf[o[u] * Q + w];
-        }
-    }
 }
 
 }  // namespace
@@ -197,33 +126,16 @@ void launch_remap_staged(int words, int64_t nnz, const uint32_t* in, uint32_t* o
                          const uint16_t* doff, hipStream_t s) {
     if (nnz == 0) return;
     const int C = stage_chunk(words);
-#if SPT_STAGE_FORM == 0
-#if SPT_STAGE_XCD
     const int64_t nchunks = (nnz + C - 1) / C;
-    const unsigned fblocks = (unsigned)(((nchunks + 7) / 8) * 8 * (C / kRemapThreads));
-#else
-    const unsigned fblocks = (unsigned)((nnz + kRemapThreads - 1) / kRemapThreads);
-#endif
+    const unsigned blocks = (unsigned)(((nchunks + 7) / 8) * 8 * (C / kRemapThreads));
     if (words == 4)
-        hipLaunchKernelGGL((remap_flat_kernel<4, kChunk16>), dim3(fblocks), dim3(kRemapThreads), 0, s, in, out,
+        hipLaunchKernelGGL((remap_flat_kernel<4, kChunk16>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out,
                            ddst, doff, nnz);
     else if (words == 8)
-        hipLaunchKernelGGL((remap_flat_kernel<8, kChunk16 / 2>), dim3(fblocks), dim3(kRemapThreads), 0, s, in,
+        hipLaunchKernelGGL((remap_flat_kernel<8, kChunk16 / 2>), dim3(blocks), dim3(kRemapThreads), 0, s, in,
                            out, ddst, doff, nnz);
     else
-        hipLaunchKernelGGL((remap_flat_kernel<12, kChunk16 / 4>), dim3(fblocks), dim3(kRemapThreads), 0, s, in,
-                           out, ddst, doff, nnz);
-    return;
-#endif
-    const unsigned blocks = (unsigned)((nnz + C - 1) / C);
-    if (words == 4)
-        hipLaunchKernelGGL((remap_staged_kernel<4, kChunk16>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out,
-                           ddst, doff, nnz);
-    else if (words == 8)
-        hipLaunchKernelGGL((remap_staged_kernel<8, kChunk16 / 2>), dim3(blocks), dim3(kRemapThreads), 0, s, in,
-                           out, ddst, doff, nnz);
-    else
-        hipLaunchKernelGGL((remap_staged_kernel<12, kChunk16 / 4>), dim3(blocks), dim3(kRemapThreads), 0, s, in,
+        hipLaunchKernelGGL((remap_flat_kernel<12, kChunk16 / 4>), dim3(blocks), dim3(kRemapThreads), 0, s, in,
                            out, ddst, doff, nnz);
 }
 

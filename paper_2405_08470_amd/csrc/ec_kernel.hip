@@ -26,25 +26,6 @@
 #ifndef SPT_GATHER_INFLIGHT
 #define SPT_GATHER_INFLIGHT 16
 #endif
-// 0: each record is stored to its next position in the step that fetches it;
-// 1: the wave first finishes its partition's computation, then streams the
-//    partition once more and stores every record (no stores in the gather
-//    loop, whose waits would otherwise also wait for them)
-#ifndef SPT_DR_DEFERRED
-#define SPT_DR_DEFERRED 0
-#endif
-// 1: a lane reloads a factor row only when the nonzero's index differs from
-// the previous nonzero's of its group (fewer gathers, but each one becomes
-// conditional and the batch no longer issues as one); 0: every gather issued
-#ifndef SPT_GATHER_REUSE
-#define SPT_GATHER_REUSE 0
-#endif
-// with SPT_DR_DEFERRED: 1 = the deferred pass walks the partition in the
-// order of the records' destinations (dsrc), so runs of consecutive
-// destinations are stored by consecutive lanes
-#ifndef SPT_DR_SORTED
-#define SPT_DR_SORTED 0
-#endif
 
 namespace spt {
 
@@ -220,17 +201,7 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     bool first_seg = true;
     const int steps = (int)(q + (rm > 0 ? 1 : 0));
     const bool remap = a.rec_out != nullptr;
-    const bool remap_inline = remap && SPT_DR_DEFERRED == 0;
-
-    // factor rows gathered for the group's previous nonzero
-    uint32_t last_c[NG];
-    uint4 last_y[NG];
-    uint32_t cb[B][NG];
-#pragma unroll
-    for (int k = 0; k < NG; ++k) {
-        last_c[k] = 0xFFFFFFFFu;
-        last_y[k] = make_uint4(0u, 0u, 0u, 0u);
-    }
+    const bool remap_inline = remap;
 
     // carry slot of a row of this partition (-1: not a split row)
     auto slot_of = [&](int row) {
@@ -273,16 +244,7 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
                 const bool live = kb + b < cnt;
                 #pragma unroll
                 for (int k = 0; k < NG; ++k) {
-                    if (SPT_GATHER_REUSE) {
-                        const uint32_t cprev = b == 0 ? last_c[k] : cb[b - 1][k];
-                        const uint32_t c = live ? stage[a.rot[k + 1]][slot] : cprev;
-                        cb[b][k] = c;
-                        y[b][k] = b == 0 ? last_y[k] : y[b - 1][k];
-                        if (c != cprev)
-                            y[b][k] = *reinterpret_cast<const uint4*>(
-                                static_cast<const char*>(a.fac[k + 1]) +
-                                ((int64_t)c * R + li * V) * FT::kBytes);
-                    } else if (live) {
+                    if (live) {
                         y[b][k] = *reinterpret_cast<const uint4*>(
                             static_cast<const char*>(a.fac[k + 1]) +
                             ((int64_t)stage[a.rot[k + 1]][slot] * R + li * V) * FT::kBytes);
@@ -328,13 +290,6 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
                     }
                     #pragma unroll
                     for (int v = 0; v < V; ++v) acc[v] = fmaf(prod[v], val, acc[v]);
-                }
-            }
-            if (SPT_GATHER_REUSE) {
-                #pragma unroll
-                for (int k = 0; k < NG; ++k) {
-                    last_c[k] = cb[B - 1][k];
-                    last_y[k] = y[B - 1][k];
                 }
             }
         }
@@ -398,26 +353,6 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
                 cslot = pslot[1][h];
                 csum = active ? part[1][h][rk] : 0.0f;
             }
-        }
-    }
-
-    // deferred remap: the partition's records, 4 per lane in flight
-    if (remap && SPT_DR_DEFERRED != 0) {
-        const int64_t e = s + n;
-        for (int64_t p0 = s + lane; p0 < e; p0 += 4 * 64) {
-            Rec<RW> r[4];
-            int32_t o[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int64_t p = p0 + 64 * k;
-                if (p < e) {
-                    load_rec<RW>(a.rec_in, SPT_DR_SORTED ? (int64_t)a.dsrc[p] : p, r[k]);
-                    o[k] = a.nxt[p];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (p0 + 64 * k < e) store_rec<RW>(a.rec_out, o[k], r[k]);
         }
     }
 }

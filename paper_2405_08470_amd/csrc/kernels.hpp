@@ -16,8 +16,6 @@ struct EcArgs {
     const uint32_t* rec_in;    // records of mode d's stream
     uint32_t* rec_out;         // remap target in mode d+1's order, or nullptr
     const int32_t* nxt;        // [nnz] position in mode d+1 of the record at p
-    const int32_t* dsrc;       // destination-sorted remap (experimental build
-                               // only): slot q stores record dsrc[q] at nxt[q]
     const int64_t* ptr;        // [kappa+1] partition offsets of mode d
     const int32_t* psplit_ptr; // [kappa+1] split rows of each partition
     const int32_t* psplit_row;

@@ -15,8 +15,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SPT_LIBRARY may name another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("SPT_LIBRARY") or os.path.join(_HERE, "libspmttkrp.so")
+LIB_PATH = os.path.join(_HERE, "libspmttkrp.so")
 
 F32 = 0
 BF16 = 1
