@@ -1,39 +1,44 @@
 #!/usr/bin/env python3
 """All-mode spMTTKRP with dynamic remapping inside CP-ALS on one MI355X.
 
-Workload (default): the 3-mode Zipf tensor 100000 x 80000 x 2000000 with 80M
-nonzeros (indices Zipf(1.1) per mode, shuffled), FP32 values U(0,1), rank 32
-FP32 factors N(0,1) -- synthetic, seeded, shaped like the paper's 3-mode
-recommender / knowledge-base tensors.
+Headline workload: the 4-mode Zipf tensor 50000 x 50000 x 20000 x 1000 with
+1e8 nonzeros (indices Zipf(1.1) per mode, shuffled), FP32 values U(0,1),
+rank 64 FP32 factors N(0,1) -- the largest of the benchmark tensors,
+synthetic and seeded, shaped like the paper's 4-mode recommender tensor.
+`value` is its all-mode pass (each mode: the elementwise kernel, the remap
+pass into the next mode's order, the split-row fixup) in ms; `ms_per_step`
+one CP-ALS sweep (that pass plus the FP64 update of every factor and the fit).
 
 Phases (inputs resident in HBM before any timed region):
-  A  all-mode spMTTKRP with dynamic remapping (mode 0 -> 1 -> 2 -> 0), each
-     mode's elementwise kernel followed by the remap pass that writes each
-     chunk of 4096 consecutive records in destination order: K timed
-     passes -> `value` (ms per all-mode pass) and per-kernel event times;
-     then the same passes with the remap fused into the elementwise kernel
-     (every record stored at its next position from inside it);
-  B  CP-ALS sweeps (A's work plus the FP64 normal-equation update of every
-     factor): K timed steps -> `ms_per_step`;
+  A  the headline all-mode pass with FP32 factors: K timed passes -> `value`,
+     per-kernel HIP-event times -> `roofline` (dominant kernel) and the
+     pass-level fraction of HBM peak;
+  D  the same passes with BF16 factor storage and gathers (FP32 accumulation);
+  B  K CP-ALS sweeps -> `ms_per_step`;
   C  the same spMTTKRP on one mode-ordered copy per mode (no remapping) ->
-     the remapping share of A (the paper's breakdown experiment, Sec. 5.2);
-  D  A's passes with BF16 factor storage and gathers (FP32 accumulation);
-  E  the 4-mode 50000 x 50000 x 20000 x 1000 Zipf(1.1) tensor, 1e8 nonzeros,
-     rank 64: all-mode passes with FP32 and with BF16 factors, and the
-     relative difference of their outputs per mode;
-  F  the 4-mode 20000 x 20000 x 10000 x 500 tensor of 5e7 distinct uniform
-     entries of a planted rank-16 model plus N(0, 0.01^2) noise: the gradient
-     of the least-squares fit over the nonzeros (forward model at the
-     nonzeros + adjoint spMTTKRP of the residuals), timed beside the plain
-     FP32 all-mode spMTTKRP of the same tensor;
-  the FP64 oracle on a bounded sample of the A tensor on the host cores.
+     the remapping share (the paper's breakdown experiment, Sec. 5.2); the
+     remap fused into the elementwise kernel (the paper's own form); the remap
+     pass alone;
+  the 3-mode 100000 x 80000 x 2000000 tensor (8e7 nonzeros, Zipf 1.1, rank
+     32) and the 5-mode 10000 x 10000 x 5000 x 200 x 50 tensor (5e7 nonzeros,
+     Zipf 1.2, lognormal values, rank 32): phases A, B and C each;
+  F  the gradient of the least-squares CP fit over the nonzeros of the
+     4-mode planted rank-16 tensor (5e7 distinct entries plus N(0, 0.01^2)
+     noise), beside the plain FP32 all-mode pass of that tensor;
+  the library's copy kernel over 4 GiB (measured-achievable bandwidth);
+  the oracle leg, on the host only: the FP64 oracle timed on all host cores
+     and on one core over a bounded prefix of the headline tensor
+     (`cpu_baseline`), and the FP32 and BF16 results of phases A and D
+     against the oracle on sampled rows of every mode.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -44,6 +49,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "all-modes spMTTKRP ms/iter + HBM GB/s vs peak; bf16 vs fp32 at stated rel err"
 HBM_PEAK_GBPS = 8000.0
+HEADLINE = "zipf4_1e8"
+OTHERS = ("zipf3_8e7", "zipf5_5e7")
 
 
 def log(*a):
@@ -51,16 +58,14 @@ def log(*a):
 
 
 CSRC = "paper_2405_08470_amd/csrc/"
-# kernel family -> (committed counter summary, sources the kernel is built from)
-TRAFFIC = {
-    "ec_kernel": ("ec_kernel_zipf3_8e7_traffic.txt", (CSRC + "ec_kernel.hip", CSRC + "kernels.hpp")),
-    "remap_flat_kernel": ("remap_flat_kernel_zipf3_8e7_traffic.txt",
-                            (CSRC + "dr_staged.hip", CSRC + "kernels.hpp")),
+# kernel family -> sources the kernel is built from (for the profile match)
+SOURCES = {
+    "ec_kernel": (CSRC + "ec_kernel.hip", CSRC + "kernels.hpp"),
+    "remap_flat_kernel": (CSRC + "dr_staged.hip", CSRC + "kernels.hpp"),
 }
 
 
 def kernel_source_hash(sources):
-    import hashlib
     h = hashlib.sha256()
     for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -68,77 +73,68 @@ def kernel_source_hash(sources):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, kappa):
+def measured_traffic(kernel, workload, kappa):
     """HBM-side bytes per launch of the kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE, scaled by what the counters
-    read for a plain copy of known size), or None when the summary is missing
+    counter summary profiles/<family>_<workload>_traffic.txt (FETCH_SIZE and
+    WRITE_SIZE, scaled by what the counters read for the library's copy
+    kernel over a buffer of known size), or None when the summary is missing
     or was taken on other kernel sources or another partition count."""
     fam = kernel.split("<")[0]
-    if fam not in TRAFFIC:
+    if fam not in SOURCES:
         return None
-    fname, sources = TRAFFIC[fam]
     try:
-        with open(os.path.join(ROOT, "profiles", fname)) as fh:
+        with open(os.path.join(ROOT, "profiles", f"{fam}_{workload}_traffic.txt")) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
     vals = dict(l.split("=", 1) for l in lines if "=" in l and not l.startswith("#"))
-    if (vals.get("kernel_source_sha256_16") != kernel_source_hash(sources) or vals.get("kernel") != kernel
+    if (vals.get("kernel_source_sha256_16") != kernel_source_hash(SOURCES[fam]) or vals.get("kernel") != kernel
             or vals.get("kappa") != str(kappa)):
         return None
     return float(vals["bytes_per_launch"])
 
 
-def algorithmic_bytes(dims, nnz, R, rec_bytes, mode, remap):
-    """Bytes one launch of the mode's kernel must move: stream the records in
-    (and, when remapping, their next positions and the records out), read each
-    input factor once and write the output once."""
-    per_nnz = rec_bytes + (4 + rec_bytes if remap else 0)
-    fac = sum(dims[w] for w in range(len(dims)) if w != mode) * R * 4
-    return nnz * per_nnz + fac + dims[mode] * R * 4
+def ec_bytes(dims, nnz, R, rec_bytes, mode, fac_bytes=4):
+    """Algorithmic bytes of one elementwise-kernel launch for `mode`: stream
+    every record in, read every input factor once, write the output once."""
+    fac = sum(dims[w] for w in range(len(dims)) if w != mode) * R * fac_bytes
+    return nnz * rec_bytes + fac + dims[mode] * R * 4
 
 
 def remap_bytes(nnz, rec_bytes):
-    """Bytes the remap of one mode must move: read each record and its next
-    position, write the record."""
+    """Algorithmic bytes of one remap pass: read every record and its next
+    position (4 bytes), write the record.  The pass as built reads 6 bytes of
+    tables per record instead of the 4-byte next position; that 2-byte
+    difference is left out of the algorithmic figure (it is in `traffic`)."""
     return nnz * (2 * rec_bytes + 4)
 
 
-def copy_bandwidth(torch, gib=4.0, reps=10):
-    n = int(gib * (1 << 30)) // 4
-    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+def canonical_bytes(dims, nnz, R, mode):
+    """The paper-format bytes of one mode's step: 4(2N+1)-byte records (N
+    remap ids, N indices, the value) read and written, factors read once,
+    output written once."""
+    N = len(dims)
+    S_ = 4 * (2 * N + 1)
+    return nnz * 2 * S_ + sum(dims[w] for w in range(N) if w != mode) * R * 4 + dims[mode] * R * 4
+
+
+def copy_bandwidth(torch, S, gib=4.0, reps=10):
+    """GB/s of the library's copy kernel (read + write bytes / time)."""
+    nb = int(gib * (1 << 30)) // 16 * 16
+    a = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    b.copy_(a)
+    S.copy_probe(a, b)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        b.copy_(a)
+        S.copy_probe(a, b)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a[:: 1 << 20], b[:: 1 << 20]))
     del a, b
-    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
-
-
-def cpu_baseline(dims, idx, val, factors, budget_s):
-    """The oracle (plain FP64 COO loop, one thread) on the first S nonzeros
-    for every mode, scaled linearly to the whole tensor."""
-    import oracle
-    N = len(dims)
-    f64 = [np.asarray(f, dtype=np.float64) for f in factors]
-    nnz = idx.shape[1]
-    probe = min(nnz, 500_000)
-    t0 = time.perf_counter()
-    for d in range(N):
-        oracle.mttkrp(dims, idx[:, :probe], val[:probe], f64, d)
-    tp = time.perf_counter() - t0
-    S = int(min(nnz, max(probe, probe * budget_s / max(tp, 1e-6))))
-    t0 = time.perf_counter()
-    for d in range(N):
-        oracle.mttkrp(dims, idx[:, :S], val[:S], f64, d)
-    ts = time.perf_counter() - t0
-    return ts * 1e3 * nnz / S, S, ts
+    return 2.0 * nb / (ms * 1e-3) / 1e9, ok
 
 
 def timed_passes(torch, S, t, K, W, fn):
@@ -162,42 +158,143 @@ def per_call(tm, key, N):
     return [tm[key][d] / max(1, tm["calls"][d]) for d in range(N)]
 
 
-def phase_bf16_wide(torch, S, synth, K, W):
-    """Phase E: FP32 against BF16 factors on the 4-mode rank-64 workload."""
-    spec = synth.WORKLOADS["zipf4_1e8"]
+def r4(xs):
+    return [round(float(x), 4) for x in xs]
+
+
+def sample_rows(col, I, count, seed):
+    """Output rows of one mode across its degree spectrum: the hottest rows,
+    rows at log-spaced degree ranks, random non-empty rows, an empty row."""
+    deg = np.bincount(col, minlength=I)
+    order = np.argsort(-deg, kind="stable")
+    nonempty = int(np.count_nonzero(deg))
+    rows = set(int(r) for r in order[:4])
+    ranks = np.unique(np.geomspace(1, max(nonempty, 1), num=count // 2).astype(np.int64) - 1)
+    rows.update(int(order[k]) for k in ranks if k < nonempty)
+    rng = np.random.default_rng(seed)
+    ne = np.flatnonzero(deg)
+    rows.update(int(r) for r in rng.choice(ne, min(ne.size, count // 4), replace=False))
+    empty = np.flatnonzero(deg == 0)
+    rows.update(int(r) for r in empty[:1])
+    return sorted(rows)
+
+
+def run_workload(torch, S, synth, name, K, W, args, headline=False):
+    """Phases A (+D) (+B) (+C) on one workload; returns its record and, for
+    the headline, the host data the oracle leg needs."""
+    spec = synth.WORKLOADS[name]
+    if args.nnz and headline:
+        spec = synth.scaled(spec, args.nnz)
     t0 = time.perf_counter()
     dims, idx, val = synth.make_coo(spec)
-    Y = synth.make_factors(spec)
-    log(f"phase E: generated {spec.name} in {time.perf_counter() - t0:.1f}s")
-    N, R = len(dims), spec.rank
-    t = S.tensor_load_coo(dims, idx, val, prep="device")
-    del idx, val
+    Y0 = synth.make_factors(spec)
+    N, R, nnz = len(dims), spec.rank, spec.nnz
+    log(f"{name}: generated dims {dims} nnz {nnz} R {R} in {time.perf_counter() - t0:.1f}s")
+    t = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, prep="device")
     info = S.tensor_info(t)
-    f32 = [torch.from_numpy(y).cuda() for y in Y]
-    fbf = [f.to(torch.bfloat16) for f in f32]
+    rec = info["record_bytes"]
+    log(f"{name}: loaded (device planner) kappa {info['kappa']} record {rec} B prep "
+        f"{info['prep_seconds']:.2f}s max partition {info['max_load']} split rows {info['split_rows']}")
+    fac = [torch.from_numpy(np.ascontiguousarray(y)).cuda() for y in Y0]
     outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
-    res = {}
-    keep = []
-    for name, fac in (("fp32", f32), ("bf16", fbf)):
-        def run(fac=fac):
+
+    def passes(tt, factors, fuse=True):
+        def run():
             for d in range(N):
-                S.mttkrp(t, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
-        wall, tm = timed_passes(torch, S, t, K, W, run)
-        ec, rm = per_call(tm, "ec_ms", N), per_call(tm, "remap_ms", N)
-        res[name] = {"ms_per_pass": round(wall, 4), "ec_kernel_ms": [round(x, 4) for x in ec],
-                     "remap_kernel_ms": [round(x, 4) for x in rm]}
-        keep.append([o.clone() for o in outs])
-        log(f"phase E {name}: {wall:.3f} ms per all-mode pass; EC {['%.3f' % x for x in ec]} ms, "
-            f"remap {['%.3f' % x for x in rm]} ms")
-    err = [float(torch.linalg.vector_norm(keep[1][d] - keep[0][d]) / torch.linalg.vector_norm(keep[0][d]))
-           for d in range(N)]
-    log(f"phase E: BF16 vs FP32 factors, rel diff per mode {['%.2e' % e for e in err]}")
+                S.mttkrp(tt, d, factors, outs[d], flags=S.FUSE_REMAP_NEXT if fuse else 0)
+        return run
+
+    # ---- A: all-mode spMTTKRP with dynamic remapping
+    wall, tm = timed_passes(torch, S, t, K, W, passes(t, fac))
+    ec, rm, fx = per_call(tm, "ec_ms", N), per_call(tm, "remap_ms", N), per_call(tm, "fixup_ms", N)
+    log(f"{name} A: {wall:.3f} ms per all-mode pass; EC {['%.3f' % x for x in ec]} ms, remap "
+        f"{['%.3f' % x for x in rm]} ms, fixup {['%.3f' % x for x in fx]} ms")
+    b_ec = [ec_bytes(dims, nnz, R, rec, d) for d in range(N)]
+    b_rm = remap_bytes(nnz, rec)
+    b_can = [canonical_bytes(dims, nnz, R, d) for d in range(N)]
+    kern_ms = sum(ec) + sum(rm) + sum(fx)
+    res = {
+        "workload": f"{name}: {N}-mode {'x'.join(map(str, dims))}, {nnz} nonzeros, {spec.dist}"
+                    + (f"({spec.zipf_s}) shuffled" if spec.dist == "zipf" else "")
+                    + f" indices, {spec.values} values, rank {R}",
+        "kappa": info["kappa"], "record_bytes": rec, "split_rows": info["split_rows"],
+        "max_partition": info["max_load"], "prep_seconds_device_planner": round(info["prep_seconds"], 3),
+        "ms_per_pass": round(wall, 4), "ec_kernel_ms": r4(ec), "remap_kernel_ms": r4(rm), "fixup_ms": r4(fx),
+        "kernel_ms_per_pass": round(kern_ms, 4),
+        # algorithmic bytes of the implemented records / the paper's records
+        "pass_GBps_implemented": round((sum(b_ec) + N * b_rm) / (kern_ms * 1e-3) / 1e9, 1),
+        "pass_GBps_canonical": round(sum(b_can) / (wall * 1e-3) / 1e9, 1),
+        "frac_canonical_of_peak": round(sum(b_can) / (wall * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "target_ms_at_half_peak": round(sum(b_can) / (0.5 * HBM_PEAK_GBPS * 1e9) * 1e3, 3),
+    }
+    keep = {"dims": dims, "idx": idx, "val": val, "Y0": Y0, "spec": spec}
+    if headline:
+        # the dominant kernel of the pass and its roofline
+        if sum(rm) > sum(ec):
+            kernel = f"remap_flat_kernel<{rec // 4}, {S.stage_chunk(rec)}>"
+            dom_bytes, dom_ms = b_rm, sum(rm) / N
+        else:
+            kernel = f"ec_kernel<{N}, {R}, {rec // 4}>"
+            dom_bytes, dom_ms = sum(b_ec) / N, sum(ec) / N
+        keep["roofline"] = (kernel, dom_bytes, dom_ms, info["kappa"])
+        rows = [sample_rows(idx[d], dims[d], 48, seed=d) for d in range(N)]
+        keep["rows"] = rows
+        keep["fp32_rows"] = [outs[d][torch.as_tensor(rows[d], device="cuda")].cpu().numpy() for d in range(N)]
+
+    # ---- D: BF16 factor storage and gathers (headline only)
+    if headline and not args.no_bf16:
+        fb = [f.to(torch.bfloat16) for f in fac]
+        wall_d, tm_d = timed_passes(torch, S, t, K, W, passes(t, fb))
+        ec_d, rm_d = per_call(tm_d, "ec_ms", N), per_call(tm_d, "remap_ms", N)
+        b_ecd = [ec_bytes(dims, nnz, R, rec, d, fac_bytes=2) for d in range(N)]
+        res["bf16"] = {"ms_per_pass": round(wall_d, 4), "ec_kernel_ms": r4(ec_d), "remap_kernel_ms": r4(rm_d),
+                       "ec_kernel_GBps": round(sum(b_ecd) / (sum(ec_d) * 1e-3) / 1e9, 1),
+                       "speedup_vs_fp32": round(wall / wall_d, 3)}
+        keep["bf16_rows"] = [outs[d][torch.as_tensor(keep["rows"][d], device="cuda")].cpu().numpy()
+                             for d in range(N)]
+        log(f"{name} D: BF16 gathers {wall_d:.3f} ms per pass; EC {['%.3f' % x for x in ec_d]} ms")
+        del fb
+
+    # ---- C: the remap fused into the elementwise kernel, the remap alone,
+    # and one copy per mode without remapping (the remapping share)
+    if not args.no_ec_only:
+        if not args.no_fused:
+            tf = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, prep="device", remap="fused")
+            wall_f, tm_f = timed_passes(torch, S, tf, K, W, passes(tf, fac))
+            tf.free()
+            res["fused_remap"] = {"ms_per_pass": round(wall_f, 4),
+                                  "ec_remap_kernel_ms": r4(per_call(tm_f, "ec_ms", N))}
+            log(f"{name} C: remap fused into EC {wall_f:.3f} ms per pass")
+
+        def remap_only():
+            for d in range(N):
+                S.remap_for_mode(t, (d + 1) % N)
+        wall_r, _ = timed_passes(torch, S, t, K, W, remap_only)
+        res["remap_alone_ms_per_pass"] = round(wall_r, 4)
+        tc = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, copies=1, prep="device")
+        wall_c, tm_c = timed_passes(torch, S, tc, K, W, passes(tc, fac, fuse=False))
+        tc.free()
+        res["ec_only_ms_per_pass"] = round(wall_c, 4)
+        res["ec_only_kernel_ms"] = r4(per_call(tm_c, "ec_ms", N))
+        res["remap_share"] = round(1 - wall_c / wall, 4)
+        log(f"{name} C: remap alone {wall_r:.3f} ms, one copy per mode {wall_c:.3f} ms per pass "
+            f"(remap share {res['remap_share']:.3f})")
+
+    # ---- B: CP-ALS sweeps (on a copy of the factors)
+    if not args.no_als:
+        fa = [f.clone() for f in fac]
+        lam = torch.empty(R, dtype=torch.float64, device="cuda")
+        wall_b, tm_b = timed_passes(torch, S, t, K, W, lambda: S.cp_als_iter(t, fa, lam, want_fit=False))
+        fit = S.cp_als_iter(t, fa, lam, want_fit=True)
+        res["cp_als_ms_per_sweep"] = round(wall_b, 4)
+        res["cp_als_dense_ms_per_sweep"] = round(sum(tm_b["als_ms"]) / K, 4)
+        res["fit_after_sweeps"] = [W + K + 1, fit]
+        log(f"{name} B: {wall_b:.3f} ms per CP-ALS sweep; fit after {W + K + 1} sweeps {fit:.6f}")
+        del fa
     t.free()
-    return {"workload": f"{spec.name}: 4-mode {'x'.join(map(str, dims))}, {spec.nnz} nonzeros, "
-                        f"Zipf({spec.zipf_s}) shuffled, rank {R}",
-            "kappa": info["kappa"], **res,
-            "bf16_rel_diff_vs_fp32": [float("%.3g" % e) for e in err],
-            "speedup_bf16": round(res["fp32"]["ms_per_pass"] / res["bf16"]["ms_per_pass"], 3)}
+    del fac, outs
+    torch.cuda.empty_cache()
+    return res, keep
 
 
 def planted_values(idx, P, noise):
@@ -222,7 +319,7 @@ def phase_gradient(torch, S, synth, K, W):
     dims, idx, P, noise = synth.planted_parts(spec)
     val = planted_values(idx, P, noise)
     start = synth.planted_start(spec, P)
-    log(f"phase F: generated {spec.name} in {time.perf_counter() - t0:.1f}s")
+    log(f"F: generated {spec.name} in {time.perf_counter() - t0:.1f}s")
     N, R = len(dims), spec.rank
     t = S.tensor_load_coo(dims, idx, val, prep="device")
     del idx, val
@@ -231,48 +328,133 @@ def phase_gradient(torch, S, synth, K, W):
     grads = [torch.empty_like(f) for f in fac]
     outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
 
-    def grad():
-        S.cp_gradient(t, fac, grads)
-
     def plain():
         for d in range(N):
             S.mttkrp(t, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
 
-    wall_g, tm_g = timed_passes(torch, S, t, K, W, grad)
+    wall_g, tm_g = timed_passes(torch, S, t, K, W, lambda: S.cp_gradient(t, fac, grads))
+    wall_l, _ = timed_passes(torch, S, t, K, W, lambda: S.cp_loss(t, fac))
     wall_p, tm_p = timed_passes(torch, S, t, K, W, plain)
     loss_start = float(S.cp_gradient(t, fac, grads)[0].item())
     pf = [torch.from_numpy(p).cuda() for p in P]
-    loss_planted = float(S.cp_gradient(t, pf, [torch.empty_like(p) for p in pf])[0].item())
+    loss_planted = float(S.cp_loss(t, pf)[0].item())
     noise_half_ss = 0.5 * float(np.dot(noise, noise))
     t.free()
-    log(f"phase F: gradient {wall_g:.3f} ms (forward + {N} adjoint modes); plain FP32 all-mode "
-        f"spMTTKRP {wall_p:.3f} ms; loss at start {loss_start:.4g}, at the planted factors "
-        f"{loss_planted:.6g} (half the noise sum of squares {noise_half_ss:.6g})")
+    log(f"F: gradient {wall_g:.3f} ms (forward + {N} adjoint modes), loss alone {wall_l:.3f} ms; plain "
+        f"FP32 all-mode spMTTKRP {wall_p:.3f} ms; loss at the planted factors {loss_planted:.6g} "
+        f"(half the noise sum of squares {noise_half_ss:.6g})")
     return {"workload": f"{spec.name}: 4-mode {'x'.join(map(str, dims))}, {spec.nnz} distinct uniform "
                         f"nonzeros of a planted rank-{R} model + N(0, {spec.noise_sd}^2) noise",
             "kappa": info["kappa"],
-            "gradient_ms": round(wall_g, 4),
-            "adjoint_ec_kernel_ms": [round(x, 4) for x in per_call(tm_g, "ec_ms", N)],
-            "adjoint_remap_kernel_ms": [round(x, 4) for x in per_call(tm_g, "remap_ms", N)],
+            "gradient_ms": round(wall_g, 4), "loss_only_ms": round(wall_l, 4),
+            "adjoint_ec_kernel_ms": r4(per_call(tm_g, "ec_ms", N)),
+            "adjoint_remap_kernel_ms": r4(per_call(tm_g, "remap_ms", N)),
             "plain_fp32_all_mode_ms": round(wall_p, 4),
-            "plain_ec_kernel_ms": [round(x, 4) for x in per_call(tm_p, "ec_ms", N)],
-            "plain_remap_kernel_ms": [round(x, 4) for x in per_call(tm_p, "remap_ms", N)],
+            "plain_ec_kernel_ms": r4(per_call(tm_p, "ec_ms", N)),
+            "plain_remap_kernel_ms": r4(per_call(tm_p, "remap_ms", N)),
             "loss_at_start": loss_start, "loss_at_planted": loss_planted,
             "half_noise_sum_sq": noise_half_ss}
 
 
-def ablation(torch, S, dims, idx, val, fac, outs, K, W, name):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_leg(keep, budget_s, want_accuracy):
+    """The FP64 oracle on the host: timed on all cores and on one core over a
+    prefix of the headline tensor sized to the time budget (the counting sort
+    that buckets nonzeros by row is not timed), scaled to the whole tensor;
+    and the GPU's FP32 and BF16 rows against it."""
+    import oracle
+    dims, idx, val, Y0 = keep["dims"], keep["idx"], keep["val"], keep["Y0"]
+    N, nnz = len(dims), idx.shape[1]
+    f64 = [np.asarray(f, dtype=np.float64) for f in Y0]
+    threads = oracle.max_threads()
+
+    def timed(S_, nthreads):
+        sub_i, sub_v = np.ascontiguousarray(idx[:, :S_]), val[:S_]
+        tot = 0.0
+        for d in range(N):
+            bk = oracle.bucket_rows(dims, sub_i, d)
+            t0 = time.perf_counter()
+            oracle.mttkrp_parallel(dims, sub_i, sub_v, f64, d, buckets=bk, nthreads=nthreads)
+            tot += time.perf_counter() - t0
+        return tot
+
+    out = {}
+    if budget_s > 0:
+        probe = min(nnz, 2_000_000)
+        tp = timed(probe, threads)
+        S_all = int(min(nnz, max(probe, probe * budget_s / max(tp, 1e-6))))
+        t_all = timed(S_all, threads)
+        probe1 = min(nnz, 500_000)
+        tp1 = timed(probe1, 1)
+        S_one = int(min(nnz, max(probe1, probe1 * (budget_s / 3) / max(tp1, 1e-6))))
+        t_one = timed(S_one, 1)
+        ms_all = t_all * 1e3 * nnz / S_all
+        ms_one = t_one * 1e3 * nnz / S_one
+        out["cpu_baseline"] = {
+            "value": round(ms_all, 3), "unit": "ms/iter", "cores": threads, "kind": "oracle",
+            "sample": f"first {S_all} of {nnz} nonzeros of {keep['spec'].name}, all {N} modes, FP64 row-bucketed "
+                      f"COO loop on {threads} threads ({t_all:.1f} s), scaled linearly to the whole tensor",
+            "cpu_model": cpu_model(),
+            "one_core_ms_per_pass": round(ms_one, 3),
+            "one_core_sample": f"first {S_one} nonzeros ({t_one:.1f} s)"}
+        log(f"oracle: {ms_all:.0f} ms per all-mode pass on {threads} threads, {ms_one:.0f} ms on one "
+            f"({cpu_model()})")
+    if want_accuracy:
+        rows = keep["rows"]
+        acc = {"rows_per_mode": [len(r) for r in rows], "fp32_rel_err": [], "fp32_max_elem_over_abs": []}
+        Yb = [oracle.bf16_round(y) for y in Y0]
+        if "bf16_rows" in keep:
+            acc.update({"bf16_storage_rel_err": [], "bf16_kernel_rel_err": [],
+                        "bf16_kernel_max_elem_over_abs": []})
+        av = np.abs(val.astype(np.float64))
+        for d in range(N):
+            bk = oracle.bucket_rows(dims, idx, d)
+            ref = oracle.mttkrp_rows(dims, idx, val, Y0, d, rows[d], buckets=bk)
+            ab = oracle.mttkrp_rows(dims, idx, av, [np.abs(y.astype(np.float64)) for y in Y0], d, rows[d],
+                                    buckets=bk)
+            g = keep["fp32_rows"][d].astype(np.float64)
+            acc["fp32_rel_err"].append(float("%.3g" % (np.linalg.norm(g - ref) / np.linalg.norm(ref))))
+            acc["fp32_max_elem_over_abs"].append(float("%.3g" % np.max(np.abs(g - ref) / np.maximum(ab, 1e-300))))
+            if "bf16_rows" in keep:
+                refb = oracle.mttkrp_rows(dims, idx, val, Yb, d, rows[d], buckets=bk)
+                abb = oracle.mttkrp_rows(dims, idx, av, [np.abs(y.astype(np.float64)) for y in Yb], d,
+                                         rows[d], buckets=bk)
+                gb = keep["bf16_rows"][d].astype(np.float64)
+                acc["bf16_storage_rel_err"].append(float("%.3g" % (np.linalg.norm(gb - ref) / np.linalg.norm(ref))))
+                acc["bf16_kernel_rel_err"].append(float("%.3g" % (np.linalg.norm(gb - refb) / np.linalg.norm(refb))))
+                acc["bf16_kernel_max_elem_over_abs"].append(
+                    float("%.3g" % np.max(np.abs(gb - refb) / np.maximum(abb, 1e-300))))
+        out["accuracy"] = acc
+        log(f"oracle: accuracy on sampled rows {acc}")
+    return out
+
+
+def ablation(torch, S, synth, name, K, W, kappa0):
     """The all-mode pass across partition counts kappa (the analog of the
-    paper's threadblock-count sweep), with the remap fused into the
-    elementwise kernel instead of staged, with the heavy-row split off (pure
-    Alg. 1), and, for four modes or more, with each record layout: ms per
-    pass, per-mode kernel times, largest partition."""
-    N = len(dims)
+    paper's threadblock-count sweep, Sec. 5.5), with the remap fused into the
+    elementwise kernel, with the heavy-row split off (pure Alg. 1), and, for
+    four modes or more, with each record layout (Sec. 3.5): ms per pass,
+    per-mode kernel times, largest partition."""
+    spec = synth.WORKLOADS[name]
+    dims, idx, val = synth.make_coo(spec)
+    Y0 = synth.make_factors(spec)
+    N, R = len(dims), spec.rank
+    fac = [torch.from_numpy(np.ascontiguousarray(y)).cuda() for y in Y0]
+    outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
     rows = []
     settings = [(k, None, "staged", "auto") for k in (2048, 4096, 8192, 16384, 32768, 65536)]
     settings += [(8192, None, "fused", "auto"), (8192, 0, "staged", "auto")]
     if N >= 4:
-        # the record layouts (Sec. 3.5) with a kernel for this shape
         small = max(dims) <= 65536
         lays = (["half16"] if small and N != 7 else []) + (["packed"] if N <= 6 else []) + ["word32"]
         settings += [(8192, None, "staged", lay) for lay in lays]
@@ -286,11 +468,10 @@ def ablation(torch, S, dims, idx, val, fac, outs, K, W, name):
                 S.mttkrp(tt, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
         kk, ww = (K, W) if cap is None else (1, 0)
         wall, tm = timed_passes(torch, S, t, kk, ww, run)
-        ec, rm = per_call(tm, "ec_ms", N), per_call(tm, "remap_ms", N)
         t.free()
         row = {"kappa": kappa, "split": cap is None, "remap": remap, "layout": layout,
                "record_bytes": info["record_bytes"], "ms_per_pass": round(wall, 4),
-               "ec_kernel_ms": [round(x, 4) for x in ec], "remap_kernel_ms": [round(x, 4) for x in rm],
+               "ec_kernel_ms": r4(per_call(tm, "ec_ms", N)), "remap_kernel_ms": r4(per_call(tm, "remap_ms", N)),
                "max_partition": info["max_load"], "mean_partition": round(len(val) / kappa, 1)}
         log(f"ablation {row}")
         rows.append(row)
@@ -302,22 +483,21 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="zipf3_8e7",
-                    help="uniform3_1e5, zipf3_8e7 (default), zipf5_5e7 or zipf4_1e8")
-    ap.add_argument("--nnz", type=int, default=None, help="override the nonzero count")
+    ap.add_argument("--workload", default=HEADLINE,
+                    help="headline workload (default zipf4_1e8; also zipf3_8e7, zipf5_5e7, uniform3_1e5)")
+    ap.add_argument("--nnz", type=int, default=None, help="override the headline nonzero count")
     ap.add_argument("--kappa", type=int, default=0)
+    ap.add_argument("--no-others", action="store_true", help="skip the 3- and 5-mode workloads")
     ap.add_argument("--no-ec-only", action="store_true", help="skip phase C")
-    ap.add_argument("--no-fused", action="store_true", help="skip the fused-remap passes of phase A")
+    ap.add_argument("--no-fused", action="store_true", help="skip the fused-remap passes of phase C")
     ap.add_argument("--no-als", action="store_true", help="skip phase B")
     ap.add_argument("--no-bf16", action="store_true", help="skip phase D")
-    ap.add_argument("--no-wide", action="store_true", help="skip phases E and F")
-    ap.add_argument("--no-host-prep", action="store_true", help="skip the host-planner load timing")
-    ap.add_argument("--prep", choices=("device", "host"), default="device",
-                    help="planner of the timed tensors (default: device)")
+    ap.add_argument("--no-wide", action="store_true", help="skip phase F")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the oracle accuracy check")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work (0: none)")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark line: the all-mode pass across kappa, with the "
-                         "remap fused, and with the heavy-row split off (one JSON line)")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
+                         "remap fused, with the heavy-row split off and per record layout (one JSON line)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -331,237 +511,63 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
-    spec = synth.WORKLOADS[args.workload]
-    if args.nnz:
-        spec = synth.scaled(spec, args.nnz)
     K, W = args.steps, args.warmup
-    R = spec.rank
-    t0 = time.perf_counter()
-    dims, idx, val = synth.make_coo(spec)
-    Y0 = synth.make_factors(spec)
-    log(f"generated {spec.name}: dims {dims} nnz {spec.nnz} R {R} in {time.perf_counter() - t0:.1f}s")
-    N = len(dims)
-
-    prep_host = None
-    if not args.no_host_prep:
-        th = S.tensor_load_coo(dims, idx, val, kappa=args.kappa)
-        prep_host = S.tensor_info(th)["prep_seconds"]
-        th.free()
-        log(f"host planner load: {prep_host:.2f}s")
-    t = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, prep=args.prep)
-    info = S.tensor_info(t)
-    log(f"loaded ({args.prep} planner): kappa {info['kappa']} record {info['record_bytes']} B prep "
-        f"{info['prep_seconds']:.2f}s max partition {info['max_load']} split rows {info['split_rows']}")
-    fac = [torch.from_numpy(np.ascontiguousarray(y)).cuda() for y in Y0]
-    outs = [torch.empty((dims[d], R), dtype=torch.float32, device="cuda") for d in range(N)]
     if args.ablation:
-        t.free()
-        print(json.dumps(ablation(torch, S, dims, idx, val, fac, outs, K, W, spec.name)), flush=True)
+        print(json.dumps(ablation(torch, S, synth, args.workload, K, W, args.kappa)), flush=True)
         return 0
 
-    def all_modes(tt, fuse):
-        for d in range(N):
-            S.mttkrp(tt, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT if fuse else 0)
+    head, keep = run_workload(torch, S, synth, args.workload, K, W, args, headline=True)
+    others = {}
+    if not args.no_others:
+        for name in OTHERS:
+            if name != args.workload:
+                others[name], _ = run_workload(torch, S, synth, name, K, W, args)
+    grad = None if args.no_wide else phase_gradient(torch, S, synth, K, W)
+    copy_gbps, copy_ok = copy_bandwidth(torch, S)
+    log(f"library copy kernel: {copy_gbps:.0f} GB/s (checked {copy_ok})")
+    orc = oracle_leg(keep, args.cpu_budget, not args.no_accuracy)
 
-    # ---- phase A: all-mode spMTTKRP with dynamic remapping (staged remap pass)
-    for _ in range(W):
-        all_modes(t, True)
-    torch.cuda.synchronize()
-    S.timing_control(t, True, want=False)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for _ in range(K):
-        all_modes(t, True)
-    torch.cuda.synchronize()
-    wall_a = (time.perf_counter() - w0) * 1e3 / K
-    tm_a = S.timing_control(t, False)
-    ec_ms = per_call(tm_a, "ec_ms", N)
-    rm_ms = per_call(tm_a, "remap_ms", N)
-    fix_ms = per_call(tm_a, "fixup_ms", N)
-    log(f"phase A: {wall_a:.3f} ms per all-mode pass; EC kernel per mode {['%.3f' % x for x in ec_ms]} ms, "
-        f"staged remap {['%.3f' % x for x in rm_ms]} ms, fixup {['%.3f' % x for x in fix_ms]} ms")
-
-    # the paper's fused form: every record stored at its next position from
-    # inside the elementwise kernel
-    fused = None
-    if not args.no_fused:
-        tf = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, prep=args.prep, remap="fused")
-
-        def fused_pass():
-            for d in range(N):
-                S.mttkrp(tf, d, fac, outs[d], flags=S.FUSE_REMAP_NEXT)
-        wall_f, tm_f = timed_passes(torch, S, tf, K, W, fused_pass)
-        tf.free()
-        ec_f = per_call(tm_f, "ec_ms", N)
-        fused = {"ms_per_pass": round(wall_f, 4), "ec_remap_kernel_ms": [round(x, 4) for x in ec_f]}
-        log(f"fused remap: {wall_f:.3f} ms per all-mode pass; EC+remap kernel {['%.3f' % x for x in ec_f]} ms")
-
-    # the remap alone (spt_remap_for_mode, one hop per call: the remap pass
-    # without the elementwise kernel), N hops per pass
-    def remap_pass():
-        for d in range(N):
-            S.remap_for_mode(t, (d + 1) % N)
-    wall_r, _ = timed_passes(torch, S, t, K, W, remap_pass)
-    log(f"remap alone: {wall_r:.3f} ms per pass of {N} one-hop remaps")
-
-    rec = info["record_bytes"]
-    bytes_ec = [algorithmic_bytes(dims, spec.nnz, R, rec, d, False) for d in range(N)]
-    bytes_rm = remap_bytes(spec.nnz, rec)
-    # the whole step of one mode: elementwise kernel + remap
-    bytes_a = [b + bytes_rm for b in bytes_ec]
-    pass_gbps = sum(bytes_a) / ((sum(ec_ms) + sum(rm_ms)) * 1e-3) / 1e9
-    canon = 4 * (2 * N + 1)
-    bytes_canon = [spec.nnz * 2 * canon + sum(dims[w] for w in range(N) if w != d) * R * 4 + dims[d] * R * 4
-                   for d in range(N)]
-    # the dominant kernel of the pass and its roofline
-    if sum(rm_ms) > sum(ec_ms):
-        kernel = f"remap_flat_kernel<{rec // 4},{S.stage_chunk(rec)}>"
-        dom_bytes, dom_ms = bytes_rm, sum(rm_ms) / N
-    else:
-        kernel = f"ec_kernel<{N},{R},{rec // 4}>"
-        dom_bytes, dom_ms = sum(bytes_ec) / N, sum(ec_ms) / N
+    kernel, dom_bytes, dom_ms, kappa = keep["roofline"]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-
-    # ---- phase D: the same passes with BF16 factor gathers (FP32 accumulation)
-    bf16 = None
-    if not args.no_bf16:
-        ref = [o.clone() for o in outs]          # FP32-gather results of phase A
-        fac32 = fac
-        fac = [f.to(torch.bfloat16) for f in fac32]
-        for _ in range(W):
-            all_modes(t, True)
-        torch.cuda.synchronize()
-        S.timing_control(t, True, want=False)
-        w0 = time.perf_counter()
-        for _ in range(K):
-            all_modes(t, True)
-        torch.cuda.synchronize()
-        wall_d = (time.perf_counter() - w0) * 1e3 / K
-        tm_d = S.timing_control(t, False)
-        ec_d, rm_d = per_call(tm_d, "ec_ms", N), per_call(tm_d, "remap_ms", N)
-        err = [float(torch.linalg.vector_norm(outs[d] - ref[d]) / torch.linalg.vector_norm(ref[d]))
-               for d in range(N)]
-        bytes_d = [b - (sum(dims[w] for w in range(N) if w != d) * R * 2) for d, b in enumerate(bytes_ec)]
-        bf16 = {"ms_per_pass": round(wall_d, 4), "ec_kernel_ms": [round(x, 4) for x in ec_d],
-                "remap_kernel_ms": [round(x, 4) for x in rm_d],
-                "rel_err_vs_fp32_gather": [float("%.3g" % e) for e in err],
-                "ec_kernel_GBps": round(sum(bytes_d) / (sum(ec_d) * 1e-3) / 1e9, 1)}
-        fac = fac32
-        del ref
-        log(f"phase D: BF16 gathers {wall_d:.3f} ms per all-mode pass; EC "
-            f"{['%.3f' % x for x in ec_d]} ms; rel err vs FP32 gathers {['%.2e' % e for e in err]}")
-
-    # ---- phase B: CP-ALS sweeps
-    ms_step = None
-    als_ms = None
-    fit = None
-    if not args.no_als:
-        lam = torch.empty(R, dtype=torch.float64, device="cuda")
-        for _ in range(W):
-            S.cp_als_iter(t, fac, lam, want_fit=False)
-        torch.cuda.synchronize()
-        S.timing_control(t, True, want=False)
-        w0 = time.perf_counter()
-        for _ in range(K):
-            S.cp_als_iter(t, fac, lam, want_fit=False)
-        torch.cuda.synchronize()
-        ms_step = (time.perf_counter() - w0) * 1e3 / K
-        tm_b = S.timing_control(t, False)
-        als_ms = sum(tm_b["als_ms"]) / K
-        fit = S.cp_als_iter(t, fac, lam, want_fit=True)
-        log(f"phase B: {ms_step:.3f} ms per CP-ALS sweep (dense FP64 step {als_ms:.3f} ms, beside the remap "
-            f"pass on a side stream); fit after "
-            f"{W + K + 1} sweeps {fit:.6f}")
-    t.free()
-
-    # ---- phase C: one mode-ordered copy per mode, no remapping
-    ec_only = None
-    ec_only_kernel = None
-    if not args.no_ec_only:
-        tc = S.tensor_load_coo(dims, idx, val, kappa=args.kappa, copies=1, prep=args.prep)
-        for _ in range(W):
-            all_modes(tc, False)
-        torch.cuda.synchronize()
-        S.timing_control(tc, True, want=False)
-        w0 = time.perf_counter()
-        for _ in range(K):
-            all_modes(tc, False)
-        torch.cuda.synchronize()
-        ec_only = (time.perf_counter() - w0) * 1e3 / K
-        tm_c = S.timing_control(tc, False)
-        ec_only_kernel = [tm_c["ec_ms"][d] / max(1, tm_c["calls"][d]) for d in range(N)]
-        tc.free()
-        log(f"phase C: {ec_only:.3f} ms per all-mode pass without remapping; kernels "
-            f"{['%.3f' % x for x in ec_only_kernel]} ms")
-
-    copy_gbps = copy_bandwidth(torch)
-    log(f"plain copy (torch) {copy_gbps:.0f} GB/s")
-
-    cpu = None
-    if args.cpu_budget > 0:
-        ms_full, S_n, ts = cpu_baseline(dims, idx, val, Y0, args.cpu_budget)
-        cpu = {"value": round(ms_full, 3), "unit": "ms/iter", "cores": 1, "kind": "oracle",
-               "sample": f"first {S_n} of {spec.nnz} nonzeros, all {N} modes, FP64 COO loop "
-                         f"({ts:.1f} s), scaled linearly to the whole tensor"}
-        log(f"cpu oracle: {ms_full:.0f} ms per all-mode pass (extrapolated from {S_n} nonzeros)")
-
-    wide_bf16 = wide_grad = None
-    if not args.no_wide:
-        del idx, val
-        wide_bf16 = phase_bf16_wide(torch, S, synth, K, W)
-        wide_grad = phase_gradient(torch, S, synth, K, W)
-
-    traffic = measured_traffic(kernel, info["kappa"])
+    traffic = measured_traffic(kernel, args.workload if not args.nnz else "", kappa)
+    dims = keep["dims"]
+    spec = keep["spec"]
     line = {
         "metric": METRIC,
-        "value": round(wall_a, 4),
+        "value": head["ms_per_pass"],
         "unit": "ms/iter",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(ms_step, 4) if ms_step is not None else round(wall_a, 4),
+        "ms_per_step": head.get("cp_als_ms_per_sweep", head["ms_per_pass"]),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{spec.name}: {N}-mode {'x'.join(map(str, dims))}, {spec.nnz} nonzeros, "
-                        f"{spec.dist}" + (f"({spec.zipf_s}) shuffled" if spec.dist == "zipf" else "")
-                        + f" indices, {spec.values} values, rank {R} FP32 factors",
-            "dims": list(dims), "nnz": spec.nnz, "rank": R, "kappa": info["kappa"],
-            "record_bytes": rec, "step": "one CP-ALS sweep (all modes: spMTTKRP + remap + FP64 update)",
+            "workload": head["workload"] + " FP32 factors",
+            "dims": list(dims), "nnz": spec.nnz, "rank": spec.rank, "kappa": head["kappa"],
+            "record_bytes": head["record_bytes"],
+            "value": "one all-mode pass: per mode the elementwise kernel, the remap pass, the split-row fixup",
+            "step": "one CP-ALS sweep (all modes: spMTTKRP + remap + FP64 update + fit)",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": round(traffic) if traffic is not None else None, "kernel": kernel,
             "bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(dom_ms, 4),
+            "pass_frac_implemented": round(head["pass_GBps_implemented"] / HBM_PEAK_GBPS, 4),
+            "pass_frac_canonical": head["frac_canonical_of_peak"],
+            "copy_kernel_GBps": round(copy_gbps, 1),
         },
-        "cpu_baseline": cpu,
+        "cpu_baseline": orc.get("cpu_baseline"),
         "breakdown": {
-            "ec_kernel_ms": [round(x, 4) for x in ec_ms],
-            "remap_kernel_ms": [round(x, 4) for x in rm_ms],
-            "fixup_ms": [round(x, 4) for x in fix_ms],
-            "pass_GBps": round(pass_gbps, 1),
-            "pass_frac": round(pass_gbps / HBM_PEAK_GBPS, 4),
-            "fused_remap": fused,
-            "als_dense_ms_per_sweep": round(als_ms, 4) if als_ms is not None else None,
-            "als_dense_overlaps_remap": True,
-            "ec_only_ms_per_pass": round(ec_only, 4) if ec_only is not None else None,
-            "ec_only_kernel_ms": [round(x, 4) for x in ec_only_kernel] if ec_only_kernel else None,
-            "remap_share": round(1 - ec_only / wall_a, 4) if ec_only is not None else None,
-            "remap_alone_ms_per_pass": round(wall_r, 4),
-            "canonical_record_GBps": round(sum(bytes_canon) / ((sum(ec_ms) + sum(rm_ms)) * 1e-3) / 1e9, 1),
-            "fit": fit,
-            "bf16_gather": bf16,
-            "bf16_rank64_4mode": wide_bf16,
-            "gradient_rank16_4mode": wide_grad,
-            f"prep_seconds_{args.prep}_planner": round(info["prep_seconds"], 3),
-            "prep_seconds_host_planner": round(prep_host, 3) if prep_host is not None else None,
+            args.workload: head,
+            **others,
+            "gradient_rank16_4mode": grad,
+            "accuracy_vs_oracle": orc.get("accuracy"),
             "copy_GBps": round(copy_gbps, 1),
-            "split_rows": info["split_rows"],
-            "max_partition": info["max_load"],
         },
     }
     print(json.dumps(line), flush=True)

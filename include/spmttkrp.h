@@ -201,6 +201,35 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void *const *factors, spt_dtype fdtyp
 spt_status spt_cp_gradient(spt_tensor_t t, const void *const *factors, spt_dtype fdtype,
                            int32_t rank, void *const *grads, double *loss, void *stream);
 
+/*
+ * spt_cp_loss -- the forward half of spt_cp_gradient: m_e at every nonzero,
+ * the residual stream (kept by the handle for spt_cp_adjoint) and
+ *   loss = 1/2 sum_e (x_e - m_e)^2   (device double[1], overwritten).
+ * Arguments, requirements and errors as spt_cp_gradient; no adjoint runs.
+ */
+spt_status spt_cp_loss(spt_tensor_t t, const void *const *factors, spt_dtype fdtype,
+                       int32_t rank, double *loss, void *stream);
+
+/*
+ * spt_cp_adjoint -- the backward half of spt_cp_gradient: grads[d] = the
+ * MTTKRP of the residual stream of the last spt_cp_loss (or
+ * spt_cp_gradient) call on this handle, for every mode d (Eq. (1) with the
+ * residuals as values).  `factors` must be the ones that call was given.  The
+ * residual stream is left in mode 0's order, so the call may be repeated.
+ * Errors: STATE (no residual stream of this rank yet), UNSUPPORTED, HIP, OOM.
+ */
+spt_status spt_cp_adjoint(spt_tensor_t t, const void *const *factors, spt_dtype fdtype,
+                          int32_t rank, void *const *grads, void *stream);
+
+/*
+ * spt_copy_probe -- copies `bytes` (a multiple of 16) from device src to
+ * device dst with a plain streaming kernel: the copy bandwidth the device
+ * reaches, reported beside the HBM peak, and a kernel of known traffic for
+ * calibrating memory counters.  Both pointers 16-byte aligned; the ranges
+ * must not overlap.  Errors: INVALID_ARG, HIP.
+ */
+spt_status spt_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
+
 /* spt_tensor_info -- fills *info (host). */
 spt_status spt_tensor_info(spt_tensor_t t, spt_info *info);
 

@@ -10,6 +10,10 @@ What is computed, and from which passage of the paper:
 
 * ``mttkrp``      Eq. (1) (Sec. 2.1.4) elementwise as in Sec. 2.1.5 / Alg. 2;
                   a plain FP64 loop over COO nonzeros (``oracle.c``).
+* ``mttkrp_parallel``  the same loop on all host cores: nonzeros bucketed by
+                  output row, each row's terms added in input order by the
+                  thread that owns the row, so the result is the plain loop's
+                  bit for bit.
 * ``plan``        Alg. 1 (Sec. 3.4): per-mode vertex ordering by degree and
                   least-filled assignment to kappa blocks; remap ids (Sec. 3.4,
                   3.5) as positions in each mode's stream; partition offsets.
@@ -40,7 +44,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compiles oracle.c into liboracle.so with gcc."""
     if force or not os.path.exists(_SO):
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", _SO,
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", _SO,
                                os.path.join(_HERE, "oracle.c")])
     return _SO
 
@@ -48,13 +52,25 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        src = os.path.join(_HERE, "oracle.c")
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
             build()
         lib = ctypes.CDLL(_SO)
         lib.orc_mttkrp.restype = ctypes.c_int
         lib.orc_mttkrp.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_void_p]
+        lib.orc_bucket_rows.restype = ctypes.c_int
+        lib.orc_bucket_rows.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+        lib.orc_mttkrp_bucketed.restype = ctypes.c_int
+        lib.orc_mttkrp_bucketed.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_int, ctypes.c_void_p]
+        lib.orc_max_threads.restype = ctypes.c_int
+        lib.orc_max_threads.argtypes = []
         lib.orc_lpt.restype = ctypes.c_int
         lib.orc_lpt.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                 ctypes.c_void_p]
@@ -92,32 +108,68 @@ def mttkrp(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
     return out
 
 
-def mttkrp_rows(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
-                factors: Sequence[np.ndarray], mode: int, rows: Sequence[int]) -> np.ndarray:
-    """Eq. (1) restricted to the listed output rows: FP64 [len(rows), R].
+def max_threads() -> int:
+    """Threads ``mttkrp_parallel`` uses by default (OpenMP's)."""
+    return int(_load().orc_max_threads())
 
-    For full-size tensors, where only sampled rows are checked.  The nonzeros
-    of the listed rows are found by a scan over i_mode; each contributes
-    val_e times the product of the other modes' factor rows, summed per row
-    column by column (``np.bincount`` with weights, in FP64)."""
-    rows = np.asarray(rows, dtype=np.int64)
-    uniq = np.unique(rows)
+
+def bucket_rows(dims: Sequence[int], idx: np.ndarray, mode: int):
+    """Row buckets of one mode: (rowptr [I+1], perm [nnz]) with the nonzeros
+    of row i, in input order, at perm[rowptr[i]:rowptr[i+1]]."""
+    lib = _load()
+    nnz = int(idx.shape[1])
+    dims64 = np.ascontiguousarray(dims, dtype=np.int64)
+    idx32 = np.ascontiguousarray(idx, dtype=np.int32)
+    rowptr = np.empty(int(dims[mode]) + 1, dtype=np.int64)
+    perm = np.empty(max(nnz, 1), dtype=np.int64)
+    if lib.orc_bucket_rows(len(dims), _ptr(dims64), nnz, _ptr(idx32), mode, _ptr(rowptr), _ptr(perm)) != 0:
+        raise ValueError("oracle bucket_rows: bad argument or index out of range")
+    return rowptr, perm
+
+
+def mttkrp_parallel(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
+                    factors: Sequence[np.ndarray], mode: int, buckets=None,
+                    nthreads: int = 0, rows: Optional[Sequence[int]] = None) -> np.ndarray:
+    """``mttkrp`` on all host cores (``nthreads`` <= 0: OpenMP's default):
+    identical to it bit for bit.  ``buckets`` = ``bucket_rows(...)`` of the
+    same mode, computed here if not given.  With ``rows``, only those output
+    rows, in the order listed: [len(rows), R]."""
+    lib = _load()
+    N = len(dims)
+    nnz = int(val.shape[0])
+    if buckets is None:
+        buckets = bucket_rows(dims, idx, mode)
+    rowptr, perm = buckets
+    dims64 = np.ascontiguousarray(dims, dtype=np.int64)
+    idx32 = np.ascontiguousarray(idx, dtype=np.int32)
+    v64 = np.ascontiguousarray(val, dtype=np.float64)
     R = int(factors[0].shape[1])
-    acc = np.zeros((uniq.size, R), dtype=np.float64)
-    col = np.asarray(idx[mode])
-    pos = np.searchsorted(uniq, col)
-    hit = np.flatnonzero(uniq[np.minimum(pos, uniq.size - 1)] == col)
-    step = 1 << 20
-    for a in range(0, hit.size, step):
-        e = hit[a:a + step]
-        term = np.repeat(np.asarray(val[e], dtype=np.float64)[:, None], R, axis=1)
-        for w in range(len(dims)):
-            if w != mode:
-                term *= np.asarray(factors[w], dtype=np.float64)[idx[w, e]]
-        loc = pos[e]
-        for r in range(R):
-            acc[:, r] += np.bincount(loc, weights=term[:, r], minlength=uniq.size)
-    return acc[np.searchsorted(uniq, rows)]
+    f64 = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+    ptrs = (ctypes.c_void_p * N)(*[_ptr(f) for f in f64])
+    if rows is None:
+        rl, nrows, nout = None, 0, int(dims[mode])
+    else:
+        rl = np.ascontiguousarray(rows, dtype=np.int64)
+        nrows = nout = int(rl.shape[0])
+    out = np.empty((nout, R), dtype=np.float64)
+    if nthreads <= 0:
+        # small tensors: one thread (a parallel region costs more than the sum)
+        nthreads = 0 if nnz >= (1 << 20) else 1
+    rc = lib.orc_mttkrp_bucketed(N, _ptr(dims64), nnz, _ptr(idx32), _ptr(v64), ptrs, R, mode,
+                                 _ptr(rowptr), _ptr(perm), None if rl is None else _ptr(rl), nrows,
+                                 int(nthreads), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle mttkrp_parallel: bad argument or index out of range")
+    return out
+
+
+def mttkrp_rows(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
+                factors: Sequence[np.ndarray], mode: int, rows: Sequence[int],
+                buckets=None) -> np.ndarray:
+    """Eq. (1) restricted to the listed output rows: FP64 [len(rows), R], the
+    rows of ``mttkrp`` bit for bit (for full-size tensors, where only sampled
+    rows are checked)."""
+    return mttkrp_parallel(dims, idx, val, factors, mode, buckets=buckets, rows=rows)
 
 
 # ---------------------------------------------------------------------------
@@ -369,13 +421,15 @@ def cp_als(dims: Sequence[int], idx: np.ndarray, val: np.ndarray,
     Y = [np.asarray(f, dtype=np.float64).copy() for f in factors]
     grams = [y.T @ y for y in Y]
     normX2 = norm_sq(dims, idx, val)
+    # MTTKRP on all host cores: the plain loop's result bit for bit
+    buckets = [bucket_rows(dims, idx, d) for d in range(N)]
     fits = []
     lam = np.ones(Y[0].shape[1])
     for _ in range(iters):
         M = None
         for d in range(N):
             G = Y if gather is None else [gather(y) for y in Y]
-            M = mttkrp(dims, idx, val, G, d)
+            M = mttkrp_parallel(dims, idx, val, G, d, buckets=buckets[d])
             Y[d], lam = als_update(M, grams, d)
             grams[d] = Y[d].T @ Y[d]
         fits.append(fit_from(normX2, M, Y[N - 1], lam, grams))

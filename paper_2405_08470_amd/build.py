@@ -20,7 +20,8 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["plan.cpp", "api.cpp"]
-HIP_SOURCES = ["ec_kernel.hip", "dr_staged.hip", "als_kernels.hip", "grad_kernel.hip", "device_plan.hip"]
+HIP_SOURCES = ["ec_kernel.hip", "dr_staged.hip", "als_kernels.hip", "grad_kernel.hip", "device_plan.hip",
+               "probe.hip"]
 
 # Packed FP32 arithmetic is disabled for all device code: the compiler would
 # otherwise emit v_pk_{add,mul,fma}_f32 from plain float code.

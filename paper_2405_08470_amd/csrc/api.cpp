@@ -85,6 +85,8 @@ struct spt_tensor_s {
     double* Vinv = nullptr;
     uint16_t* shadow[8] = {};  // BF16 copies of the factors (CP-ALS with SPT_BF16)
     uint32_t* res[2] = {nullptr, nullptr};  // residual stream + its remap target
+    int res_cur = 0;                        // res[res_cur]: residuals in mode 0's order
+    int res_rank = 0;                       // rank of the last forward pass (0: none)
     double* loss_part = nullptr;
     double* Gsum = nullptr;
     double* Isum = nullptr;
@@ -808,51 +810,115 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
     return SPT_OK;
 }
 
-spt_status spt_cp_gradient(spt_tensor_t t, const void* const* factors, spt_dtype fdtype,
-                           int32_t rank, void* const* grads, double* loss, void* stream) {
-    g_last_error.clear();
+namespace {
+
+// Checks shared by the loss, the adjoint and the gradient.
+spt_status grad_args(spt_tensor_t t, const void* const* factors, spt_dtype fdtype, int32_t rank) {
     if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
     if (fdtype != SPT_F32) return fail(SPT_ERR_UNSUPPORTED, "gradient supports FP32 factors");
     if (!als_rank(rank)) return fail(SPT_ERR_UNSUPPORTED, "gradient rank must be 8, 16, 32 or 64");
-    if (!factors || !grads || !loss) return fail(SPT_ERR_INVALID_ARG, "NULL factors, grads or loss");
+    if (!factors) return fail(SPT_ERR_INVALID_ARG, "NULL factors");
     for (int w = 0; w < t->N; ++w)
-        if (!factors[w] || !grads[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor or gradient");
+        if (!factors[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor matrix");
     if (!t->copies && t->cur_mode != 0) return fail(SPT_ERR_STATE, "stream must be in mode 0's order");
-    hipStream_t s = (hipStream_t)stream;
     spt_status st = ensure_carry(t, rank);
     if (st != SPT_OK) return st;
-    const int W = t->lay.words;
     if (!t->res[0]) {
         const int nres = t->copies ? 1 : 2;
         for (int k = 0; k < nres; ++k)
-            if ((st = dalloc(t, &t->res[k], (size_t)(t->nnz * W), &t->allocs)) != SPT_OK) return st;
+            if ((st = dalloc(t, &t->res[k], (size_t)(t->nnz * t->lay.words), &t->allocs)) != SPT_OK) return st;
         if ((st = dalloc(t, &t->loss_part, (size_t)spt::forward_blocks(t->nnz), &t->allocs)) != SPT_OK)
             return st;
     }
+    return SPT_OK;
+}
+
+// Forward pass over the mode-0 stream: the residual stream into res[0] and
+// the loss into loss[0].
+spt_status run_loss(spt_tensor_t t, const void* const* factors, int32_t rank, double* loss, hipStream_t s) {
+    const uint32_t* src = t->copies ? t->rec_mode[0] : t->rec[t->cur];
+    spt_status st = launch_forward_pass(t, src, t->res[0], factors, rank, s);
+    if (st != SPT_OK) return st;
+    spt::launch_reduce_partials(t->loss_part, spt::forward_blocks(t->nnz), 1, loss, s);
+    HIPCHK(hipGetLastError());
+    t->res_rank = rank;
+    t->res_cur = 0;
+    return SPT_OK;
+}
+
+// The adjoint of every mode from the residual stream of the last forward
+// pass (res[res_cur], mode 0's order), remapped mode to mode and back to
+// mode 0's order.  With one copy per mode each mode's residuals are formed
+// again from that mode's own stream.
+spt_status run_adjoint(spt_tensor_t t, const void* const* factors, int32_t rank, void* const* grads,
+                       hipStream_t s) {
     const int N = t->N;
-    const int nb = spt::forward_blocks(t->nnz);
+    spt_status st;
     if (t->copies) {
-        // each mode's own stream: residuals in that order, then its MTTKRP
         for (int d = 0; d < N; ++d) {
-            if ((st = launch_forward_pass(t, t->rec_mode[d], t->res[0], factors, rank, s)) != SPT_OK)
+            if (d > 0 && (st = launch_forward_pass(t, t->rec_mode[d], t->res[0], factors, rank, s)) != SPT_OK)
                 return st;
-            if (d == 0) spt::launch_reduce_partials(t->loss_part, nb, 1, loss, s);
             if ((st = launch_mode(t, d, t->res[0], nullptr, factors, SPT_F32, rank, (float*)grads[d], s)) != SPT_OK)
                 return st;
         }
+        // res[0] now holds the last mode's residuals: form mode 0's again
+        if (N > 1) return launch_forward_pass(t, t->rec_mode[0], t->res[0], factors, rank, s);
         return SPT_OK;
     }
-    // residual stream in mode 0's order, then the adjoint MTTKRP of every mode
-    // with the residual stream remapped from mode to mode (back to mode 0)
-    if ((st = launch_forward_pass(t, t->rec[t->cur], t->res[0], factors, rank, s)) != SPT_OK) return st;
-    spt::launch_reduce_partials(t->loss_part, nb, 1, loss, s);
-    int cur = 0;
+    int cur = t->res_cur;
     for (int d = 0; d < N; ++d) {
-        if ((st = launch_mode(t, d, t->res[cur], t->res[1 - cur], factors, SPT_F32, rank,
-                              (float*)grads[d], s)) != SPT_OK)
+        if ((st = launch_mode(t, d, t->res[cur], t->res[1 - cur], factors, SPT_F32, rank, (float*)grads[d],
+                              s)) != SPT_OK)
             return st;
         cur = 1 - cur;
     }
+    t->res_cur = cur;  // N remaps: mode 0's order again
+    return SPT_OK;
+}
+
+}  // namespace
+
+spt_status spt_cp_loss(spt_tensor_t t, const void* const* factors, spt_dtype fdtype, int32_t rank,
+                       double* loss, void* stream) {
+    g_last_error.clear();
+    spt_status st = grad_args(t, factors, fdtype, rank);
+    if (st != SPT_OK) return st;
+    if (!loss) return fail(SPT_ERR_INVALID_ARG, "NULL loss");
+    return run_loss(t, factors, rank, loss, (hipStream_t)stream);
+}
+
+spt_status spt_cp_adjoint(spt_tensor_t t, const void* const* factors, spt_dtype fdtype, int32_t rank,
+                          void* const* grads, void* stream) {
+    g_last_error.clear();
+    spt_status st = grad_args(t, factors, fdtype, rank);
+    if (st != SPT_OK) return st;
+    if (!grads) return fail(SPT_ERR_INVALID_ARG, "NULL grads");
+    for (int w = 0; w < t->N; ++w)
+        if (!grads[w]) return fail(SPT_ERR_INVALID_ARG, "NULL gradient matrix");
+    if (t->res_rank != rank) return fail(SPT_ERR_STATE, "no residual stream of this rank: call spt_cp_loss first");
+    return run_adjoint(t, factors, rank, grads, (hipStream_t)stream);
+}
+
+spt_status spt_cp_gradient(spt_tensor_t t, const void* const* factors, spt_dtype fdtype,
+                           int32_t rank, void* const* grads, double* loss, void* stream) {
+    g_last_error.clear();
+    spt_status st = grad_args(t, factors, fdtype, rank);
+    if (st != SPT_OK) return st;
+    if (!grads || !loss) return fail(SPT_ERR_INVALID_ARG, "NULL grads or loss");
+    for (int w = 0; w < t->N; ++w)
+        if (!grads[w]) return fail(SPT_ERR_INVALID_ARG, "NULL gradient matrix");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = run_loss(t, factors, rank, loss, s)) != SPT_OK) return st;
+    return run_adjoint(t, factors, rank, grads, s);
+}
+
+spt_status spt_copy_probe(const void* src, void* dst, int64_t bytes, void* stream) {
+    g_last_error.clear();
+    if (bytes < 0 || bytes % 16 != 0) return fail(SPT_ERR_INVALID_ARG, "bytes must be a non-negative multiple of 16");
+    if (bytes > 0 && (!src || !dst)) return fail(SPT_ERR_INVALID_ARG, "NULL src or dst");
+    if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return fail(SPT_ERR_INVALID_ARG, "src and dst must be 16-byte aligned");
+    spt::launch_copy_probe(src, dst, bytes, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
     return SPT_OK;
 }
 

@@ -94,6 +94,8 @@ void launch_als_finish(int rank, int nmodes, int mode, const double* Gun, const 
                        double* grams, double* lambda, double normX2, int want_fit, double* fit,
                        hipStream_t s);
 void launch_scale_cols(int rank, float* Y, int64_t rows, const double* lambda, hipStream_t s);
+// dst[0..bytes) = src[0..bytes), bytes a multiple of 16 (probe.hip)
+void launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s);
 // p[0..n) = 0 with a kernel (no memset node when a caller captures a graph)
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);
 

@@ -56,9 +56,9 @@ class spt_timing(ctypes.Structure):
 
 
 EXPORTS = ["spt_tensor_load_coo", "spt_remap_for_mode", "spt_mttkrp", "spt_cp_als_iter",
-           "spt_cp_gradient", "spt_tensor_info", "spt_tensor_get_remap", "spt_tensor_get_records",
-           "spt_timing_control", "spt_tensor_free", "spt_plan_coo", "spt_status_str",
-           "spt_last_error"]
+           "spt_cp_gradient", "spt_cp_loss", "spt_cp_adjoint", "spt_copy_probe", "spt_tensor_info",
+           "spt_tensor_get_remap", "spt_tensor_get_records", "spt_timing_control", "spt_tensor_free",
+           "spt_plan_coo", "spt_status_str", "spt_last_error"]
 
 _lib = None
 
@@ -76,6 +76,9 @@ def lib() -> ctypes.CDLL:
     L.spt_mttkrp.argtypes = [vp, i32, vp, i32, i32, vp, ctypes.c_uint32, vp]
     L.spt_cp_als_iter.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.spt_cp_gradient.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    L.spt_cp_loss.argtypes = [vp, vp, i32, i32, vp, vp]
+    L.spt_cp_adjoint.argtypes = [vp, vp, i32, i32, vp, vp]
+    L.spt_copy_probe.argtypes = [vp, vp, i64, vp]
     L.spt_tensor_info.argtypes = [vp, vp]
     L.spt_tensor_get_remap.argtypes = [vp, i32, vp]
     L.spt_tensor_get_records.argtypes = [vp, vp, vp, vp]
@@ -148,6 +151,7 @@ class Tensor:
         self.dims = tuple(int(d) for d in dims)
         self.nmodes = len(self.dims)
         self.nnz = int(nnz)
+        self._loss_gen = 0  # forward passes run (cp_loss), for CPFitLoss
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -264,29 +268,74 @@ def cp_gradient(t: Tensor, factors: Sequence[torch.Tensor], grads: Optional[List
     garr = _factor_ptrs(t, grads, rank)
     loss = torch.empty(1, dtype=torch.float64, device=factors[0].device)
     _check(lib().spt_cp_gradient(t.handle, arr, F32, rank, garr, loss.data_ptr(), _stream(stream)))
+    t._loss_gen += 1
     return loss, grads
+
+
+def cp_loss(t: Tensor, factors: Sequence[torch.Tensor], stream=None) -> torch.Tensor:
+    """loss = 1/2 sum_e (x_e - m_e)^2 over the stored nonzeros (forward kernel
+    only; the handle keeps the residual stream for ``cp_adjoint``).  Returns a
+    CUDA float64 tensor of shape (1,)."""
+    rank = int(factors[0].shape[1])
+    arr = _factor_ptrs(t, factors, rank)
+    loss = torch.empty(1, dtype=torch.float64, device=factors[0].device)
+    _check(lib().spt_cp_loss(t.handle, arr, F32, rank, loss.data_ptr(), _stream(stream)))
+    t._loss_gen += 1
+    return loss
+
+
+def cp_adjoint(t: Tensor, factors: Sequence[torch.Tensor], grads: Optional[List[torch.Tensor]] = None,
+               stream=None) -> List[torch.Tensor]:
+    """Gradient of the last ``cp_loss`` with respect to every factor: the
+    spMTTKRP of its residual stream in every mode."""
+    rank = int(factors[0].shape[1])
+    arr = _factor_ptrs(t, factors, rank)
+    if grads is None:
+        grads = [torch.empty_like(f) for f in factors]
+    garr = _factor_ptrs(t, grads, rank)
+    _check(lib().spt_cp_adjoint(t.handle, arr, F32, rank, garr, _stream(stream)))
+    return grads
 
 
 class CPFitLoss(torch.autograd.Function):
     """Least-squares CP fit over the stored nonzeros as an autograd function:
-    forward runs the model-at-nonzeros kernel, backward hands back the
-    adjoint (spMTTKRP of the residuals) computed with it."""
+    forward runs the model-at-nonzeros kernel only; backward runs the adjoint
+    (spMTTKRP of the residuals) and scales it by the incoming gradient."""
 
     @staticmethod
     def forward(ctx, t, *factors):
         fs = [f.detach().contiguous() for f in factors]
-        loss, grads = cp_gradient(t, fs)
-        ctx.save_for_backward(*grads)
+        loss = cp_loss(t, fs)
+        ctx.t = t
+        ctx.gen = t._loss_gen
+        ctx.save_for_backward(*fs)
         return loss[0]
 
     @staticmethod
     def backward(ctx, gout):
-        grads = ctx.saved_tensors
+        fs = ctx.saved_tensors
+        t = ctx.t
+        if t._loss_gen != ctx.gen:
+            # another forward ran on this tensor since: its residuals first
+            cp_loss(t, fs)
+        grads = cp_adjoint(t, fs)
         return (None,) + tuple(g * gout.to(g.dtype) for g in grads)
 
 
 def cp_fit_loss(t: Tensor, factors: Sequence[torch.Tensor]) -> torch.Tensor:
     return CPFitLoss.apply(t, *factors)
+
+
+def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """dst <- src with the library's plain streaming copy kernel (the
+    measured-achievable bandwidth); both contiguous CUDA tensors of the same
+    byte size, a multiple of 16."""
+    nb = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()
+            and dst.numel() * dst.element_size() == nb):
+        raise ValueError("src and dst must be contiguous CUDA tensors of equal byte size")
+    _check(lib().spt_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nb,
+                                _stream(stream)))
 
 
 def stage_chunk(record_bytes: int) -> int:

@@ -1,24 +1,32 @@
 """Full-size parity: the benchmark workloads at their stated sizes, in the
-launch configuration the benchmark times (default kappa, fused remap), through
-the C ABI.
+launch configuration the benchmark times (default kappa, remap pass after the
+elementwise kernel), through the C ABI.
 
 The oracle cannot run the whole MTTKRP of 1e8 nonzeros in test time, so it
-computes sampled output rows one by one (``oracle.mttkrp_rows``) on a subset
-of rank columns.  Column r of M_d depends only on column r of the factors (a
-pinned oracle property), so the columns of the GPU result are compared with
-the oracle on the factors' same columns.  Rows: the hottest rows (split across
-many partitions), a high-degree row, random non-empty rows, an empty row, the
-first and the last row.  Integer work is checked bit-exactly at full size: the
-stream after loading and after each fused remap holds record e at position
-b_d(e), and b_d is a permutation.
+computes a few hundred sampled output rows per mode (``oracle.mttkrp_rows``,
+the full loop's rows bit for bit) across the degree spectrum: the hottest rows
+(split across many partitions), rows at log-spaced degree ranks, random rows,
+empty rows, the first and the last row, on every rank column.  Each element is
+held to 1e-5 of the magnitude sum of its terms (``parity``).  Integer work is
+checked bit-exactly at full size: the stream after loading and after each
+remap holds record e at position b_d(e), and b_d is a permutation.
+
+CP-ALS at full size: one sweep's last update is checked by its backward error
+(the GPU factor times the normal matrix against the oracle's MTTKRP, element
+by element), which does not depend on the conditioning of the normal matrix,
+and ten sweeps' fits against the oracle's stored fits.
 """
 import sys
 
 import numpy as np
 import pytest
 
+import json
+import os
+
 import oracle
 from paper_2405_08470_amd import synth
+from parity import GAMMA, check_elementwise, degree_spectrum_rows, elementwise_ratio
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -37,20 +45,6 @@ def _say(*a):
 
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
-def _sample_rows(col, I, seed):
-    deg = np.bincount(col, minlength=I)
-    order = np.argsort(-deg, kind="stable")
-    rng = np.random.default_rng(seed)
-    nonempty = np.flatnonzero(deg)
-    rows = [int(order[0]), int(order[1]), int(order[len(nonempty) // 100])]
-    rows += [int(r) for r in rng.choice(nonempty, 3, replace=False)]
-    empty = np.flatnonzero(deg == 0)
-    if empty.size:
-        rows.append(int(empty[0]))
-    rows += [0, I - 1]
-    return rows
 
 
 def _check_stream(t, idx, val, mode):
@@ -78,13 +72,31 @@ def _all_modes(t, dims, fdev, R, check=None):
     return outs
 
 
-def _compare(dims, idx, val, Y, outs, cols, label):
+def _rows_and_refs(dims, idx, val, factor_sets, count=160):
+    """Sampled rows of every mode and, for each factor set, the oracle's rows
+    and their magnitude sums M_abs."""
+    out = []
+    av = np.abs(np.asarray(val, dtype=np.float64))
     for d in range(len(dims)):
-        rows = _sample_rows(idx[d], dims[d], seed=d)
-        ref = oracle.mttkrp_rows(dims, idx, val, [y[:, cols] for y in Y], d, rows)
-        got = outs[d][rows][:, cols]
+        rows = degree_spectrum_rows(idx[d], dims[d], count, seed=d)
+        bk = oracle.bucket_rows(dims, idx, d)
+        refs = []
+        for Y in factor_sets:
+            ref = oracle.mttkrp_rows(dims, idx, val, Y, d, rows, buckets=bk)
+            aY = [np.abs(np.asarray(y, dtype=np.float64)) for y in Y]
+            refs.append((ref, oracle.mttkrp_rows(dims, idx, av, aY, d, rows, buckets=bk)))
+        out.append((rows, refs))
+    return out
+
+
+def _compare(outs, samples, k, label):
+    for d, (rows, refs) in enumerate(samples):
+        ref, absref = refs[k]
+        got = outs[d][rows]
         e = _rel(got, ref)
-        _say(f"  {label} mode {d}: rows {rows[:3]}... rel {e:.2e}")
+        ratio = check_elementwise(got, ref, absref, label=f"{label} mode {d}")
+        _say(f"  {label} mode {d}: {len(rows)} rows x {got.shape[1]} columns, rel {e:.2e}, "
+             f"max element / M_abs {ratio:.2e}")
         assert e <= TOL
 
 
@@ -105,18 +117,19 @@ def test_full_size_all_modes_with_remap(name):
     _check_stream(t, idx, val, 0)
     fdev = [torch.from_numpy(y).cuda() for y in Y]
     outs = _all_modes(t, dims, fdev, R, check=lambda m: _check_stream(t, idx, val, m))
-    cols = list(range(0, R, R // 8))
-    _compare(dims, idx, val, Y, outs, cols, "fp32")
+    sets = [Y]
     if name == "zipf4_1e8":
-        # BF16 factor storage and gathers, FP32 accumulation
-        Yb = [oracle.bf16_round(y) for y in Y]
+        sets.append([oracle.bf16_round(y) for y in Y])
+    samples = _rows_and_refs(dims, idx, val, sets)
+    _compare(outs, samples, 0, "fp32")
+    if name == "zipf4_1e8":
+        # BF16 factor storage and gathers, FP32 accumulation: the kernel error
+        # against the oracle on the rounded factors, and the storage error
         fb = [f.to(torch.bfloat16) for f in fdev]
         outb = _all_modes(t, dims, fb, R)
-        _compare(dims, idx, val, Yb, outb, cols, "bf16 kernel")
-        for d in range(len(dims)):
-            rows = _sample_rows(idx[d], dims[d], seed=d)
-            ref = oracle.mttkrp_rows(dims, idx, val, [y[:, cols] for y in Y], d, rows)
-            e = _rel(outb[d][rows][:, cols], ref)
+        _compare(outb, samples, 1, "bf16 kernel")
+        for d, (rows, refs) in enumerate(samples):
+            e = _rel(outb[d][rows], refs[0][0])
             _say(f"  bf16 storage mode {d}: rel {e:.2e}")
             assert e <= 1.5e-2
     assert S.tensor_info(t)["cur_mode"] == 0
@@ -124,21 +137,23 @@ def test_full_size_all_modes_with_remap(name):
 
 
 def test_full_size_cp_als_sweep_last_mode_update_and_fit():
-    """One CP-ALS sweep at 8e7 nonzeros.  The last mode's update is the FP64
-    least-squares solution from the other (final) factors: Y_last * lambda =
-    M_last V^-1 with V the Hadamard product of the other factors' Grams.
+    """One CP-ALS sweep at 8e7 nonzeros.  The last mode's update solves
+    Y_last diag(lambda) V = M_last, V the Hadamard product of the other
+    (final) factors' Grams, M_last the MTTKRP of the last mode.
 
-    Checked two ways.  (i) The fit, which is stationary at the least-squares
-    optimum and so insensitive to the conditioning of V.  It is computed as
-    sqrt(||X||^2 + ||Xhat||^2 - 2<X, Xhat>), which cancels: an FP32-level
-    error (2^-24 relative) in the FP32 MTTKRP that <X, Xhat> is formed from
-    reaches the fit amplified by ||X|| / ||X - Xhat|| = 1 / (1 - fit), so
-    the bound is max(1e-6, 8 2^-24 / (1 - fit)).  (ii) The update
-    itself on sampled rows, within the accuracy the normal equations allow:
-    FP32 storage of M and of the factors perturbs M and V by about 2^-24
-    relative, which the solve amplifies by up to cond(V); after one sweep of a
-    skewed tensor cond(V) is in the thousands, so the bound is
-    max(1e-5, 16 cond(V) 2^-24).  Every column of Y_last has unit norm."""
+    (i) Backward error, every element: with the GPU's returned factors, the
+    oracle forms M_last (FP64) and V (FP64 Grams of the FP32 factors); then
+        |Y diag(lambda) V - M_last| <= 1e-5 M_abs + 4 u |Y| diag(lambda) |V|,
+    u = 2^-24.  The first term is the FP32 MTTKRP's element bound; the second
+    the rounding of the FP64 solution to FP32 (each entry of Y within u of
+    the exact one, carried through V), plus room for the FP64 steps.  Neither
+    grows with the conditioning of V.
+    (ii) The fit, which is stationary at the least-squares optimum.  It is
+    computed as sqrt(||X||^2 + ||Xhat||^2 - 2<X, Xhat>), which cancels: an
+    FP32-level error (2^-24 relative) in the FP32 MTTKRP that <X, Xhat> is
+    formed from reaches the fit amplified by ||X|| / ||X - Xhat|| =
+    1 / (1 - fit), so the bound is max(1e-6, 8 2^-24 / (1 - fit)).
+    Every column of Y_last has unit norm."""
     spec = synth.WORKLOADS["zipf3_8e7"]
     _say(f"case full-size CP-ALS sweep: {spec.name}")
     dims, idx, val = synth.make_coo(spec)
@@ -157,7 +172,18 @@ def test_full_size_cp_als_sweep_last_mode_update_and_fit():
     V = np.ones((R, R))
     for w in range(N - 1):
         V *= grams[w]
-    M = oracle.mttkrp(dims, idx, val, Y, d)
+    bk = oracle.bucket_rows(dims, idx, d)
+    M = oracle.mttkrp_parallel(dims, idx, val, Y, d, buckets=bk)
+    M_abs = oracle.mttkrp_parallel(dims, idx, np.abs(val.astype(np.float64)),
+                                   [np.abs(y.astype(np.float64)) for y in Y], d, buckets=bk)
+    Yd = Y[d].astype(np.float64)
+    lhs = (Yd * lam) @ V
+    u = 2.0 ** -24
+    bound = GAMMA * M_abs + 4 * u * ((np.abs(Yd) * lam) @ np.abs(V))
+    ratio = elementwise_ratio(lhs, M, bound)
+    _say(f"  backward error of the last update: max |Y lambda V - M| / bound {ratio:.3e} "
+         f"(cond(V) {float(np.linalg.cond(V)):.3g})")
+    assert ratio <= 1.0
     X = np.linalg.solve(V, M.T).T                     # M V^-1
     lam_o = np.linalg.norm(X, axis=0)
     Yn = X / lam_o
@@ -166,11 +192,34 @@ def test_full_size_cp_als_sweep_last_mode_update_and_fit():
     tol_fit = max(1e-6, 8 * 2.0 ** -24 / (1.0 - fit_o))
     _say(f"  fit gpu {fit:.9f} oracle (exact last update) {fit_o:.9f} (bound {tol_fit:.2e})")
     assert abs(fit - fit_o) <= tol_fit
-    rows = _sample_rows(idx[d], dims[d], seed=7)
-    cond = float(np.linalg.cond(V))
-    tol = max(1e-5, 16 * cond * 2.0 ** -24)
-    e = _rel(Y[d][rows].astype(np.float64) * lam, X[rows])
-    _say(f"  last-mode update on sampled rows rel {e:.2e} (cond(V) {cond:.3g}, bound {tol:.2e})")
-    assert e <= tol
-    norms = np.linalg.norm(Y[d].astype(np.float64), axis=0)
+    norms = np.linalg.norm(Yd, axis=0)
     assert np.allclose(norms[lam > 0], 1.0, atol=1e-5)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "als_fits_full.json")
+
+
+@pytest.mark.parametrize("name", ["zipf3_8e7", "zipf5_5e7"])
+def test_full_size_ten_sweep_fits(name):
+    """Ten CP-ALS sweeps on the full-size 3- and 5-mode workloads from their
+    seeded factors: the fit after every sweep against the FP64 oracle's
+    (stored by tests/golden/make_als_fits.py, which calls only the oracle).
+    ALS is not contractive, so the FP32 and FP64 trajectories may part; the
+    fits, stationary at each least-squares step, are held to 1e-4."""
+    with open(GOLDEN) as fh:
+        gold = json.load(fh)["workloads"][name]
+    spec = synth.WORKLOADS[name]
+    _say(f"case full-size ten sweeps: {spec.name}")
+    dims, idx, val = synth.make_coo(spec)
+    assert list(dims) == gold["dims"] and spec.nnz == gold["nnz"] and spec.rank == gold["rank"]
+    Y0 = synth.make_factors(spec)
+    t = S.tensor_load_coo(dims, idx, val, prep="device")
+    del idx, val
+    f = [torch.from_numpy(y).cuda() for y in Y0]
+    lam = torch.empty(spec.rank, dtype=torch.float64, device="cuda")
+    fits = [S.cp_als_iter(t, f, lam) for _ in range(len(gold["fits"]))]
+    t.free()
+    drift = [abs(a - b) for a, b in zip(fits, gold["fits"])]
+    for k, (a, b) in enumerate(zip(fits, gold["fits"])):
+        _say(f"  sweep {k + 1}: fit gpu {a:.9f} oracle {b:.9f} |diff| {abs(a - b):.2e}")
+    assert max(drift) <= 1e-4

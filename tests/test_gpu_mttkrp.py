@@ -1,8 +1,10 @@
-"""GPU parity of spMTTKRP with fused remapping against the FP64 oracle.
+"""GPU parity of spMTTKRP with remapping against the FP64 oracle.
 
-Every call goes through the C ABI.  Tolerance: per-mode relative Frobenius
-error <= 1e-5 (FP32 storage and accumulation against FP64); integer results
-(remap ids, the remapped streams) bit-exact.
+Every call goes through the C ABI.  Tolerances: every output element within
+1e-5 of the magnitude sum M_abs of its terms (``parity.check_elementwise``),
+and the per-mode relative Frobenius error <= 1e-5 (FP32 storage and
+accumulation against FP64); integer results (remap ids, the remapped streams)
+bit-exact.
 """
 import sys
 
@@ -11,6 +13,7 @@ import pytest
 
 import oracle
 from paper_2405_08470_amd import synth
+from parity import check_elementwise, mttkrp_abs
 
 pytestmark = pytest.mark.gpu
 
@@ -89,7 +92,8 @@ def test_mttkrp_all_modes_with_remap(case):
     for d in range(N):
         ref = oracle.mttkrp(dims, idx, val, Y, d)
         err = _rel(outs[d], ref)
-        _say(f"  mode {d}: rel err {err:.2e}")
+        ratio = check_elementwise(outs[d], ref, mttkrp_abs(dims, idx, val, Y, d), label=f"mode {d}")
+        _say(f"  mode {d}: rel err {err:.2e}, max element error / M_abs {ratio:.2e}")
         assert err <= TOL, (d, err)
     t.free()
 
@@ -117,12 +121,14 @@ def test_ec_only_one_copy_per_mode_and_state_errors():
     Y = synth.random_factors(dims, 16, seed=9)
     fdev = _dev(Y)
     refs = [oracle.mttkrp(dims, idx, val, Y, d) for d in range(4)]
+    absr = [mttkrp_abs(dims, idx, val, Y, d) for d in range(4)]
     # one copy per mode: any order of modes, no remapping
     tc = S.tensor_load_coo(dims, idx, val, copies=1)
     for d in (2, 0, 3, 1, 2):
         out = torch.empty((dims[d], 16), dtype=torch.float32, device="cuda")
         S.mttkrp(tc, d, fdev, out)
         assert _rel(out.cpu().numpy(), refs[d]) <= TOL
+        check_elementwise(out.cpu().numpy(), refs[d], absr[d], label=f"one copy, mode {d}")
     tc.free()
     # one copy + remap target: wrong order is an error unless auto-remap
     t = S.tensor_load_coo(dims, idx, val)
@@ -133,6 +139,7 @@ def test_ec_only_one_copy_per_mode_and_state_errors():
     S.mttkrp(t, 2, fdev, out, flags=S.AUTO_REMAP)
     assert S.tensor_info(t)["cur_mode"] == 2
     assert _rel(out.cpu().numpy(), refs[2]) <= TOL
+    check_elementwise(out.cpu().numpy(), refs[2], absr[2], label="auto remap, mode 2")
     # EC without remap leaves the order alone
     S.mttkrp(t, 2, fdev, out)
     assert S.tensor_info(t)["cur_mode"] == 2
@@ -144,6 +151,7 @@ def test_ec_only_one_copy_per_mode_and_state_errors():
     out0 = torch.empty((dims[0], 16), dtype=torch.float32, device="cuda")
     S.mttkrp(t, 0, fdev, out0, flags=S.FUSE_REMAP_NEXT)
     assert _rel(out0.cpu().numpy(), refs[0]) <= TOL
+    check_elementwise(out0.cpu().numpy(), refs[0], absr[0], label="after two hops, mode 0")
     t.free()
 
 
@@ -184,6 +192,7 @@ def test_edge_cases(kind):
             assert np.all(outs[d] == 0)
         else:
             assert _rel(outs[d], ref) <= TOL, (kind, d)
+            check_elementwise(outs[d], ref, mttkrp_abs(dims, idx, val, Y, d), label=f"{kind} mode {d}")
     assert S.tensor_info(t)["cur_mode"] == 0
     t.free()
 

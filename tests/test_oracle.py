@@ -136,7 +136,31 @@ def test_mttkrp_rows_equals_the_full_loop_on_sampled_rows(dims):
         rows = [int(np.argmax(deg)), int(np.argmin(deg)), 0, dims[d] - 1, int(np.argmax(deg))]
         got = oracle.mttkrp_rows(dims, idx, val, Y, d, rows)
         assert got.shape == (len(rows), 6)
-        assert np.allclose(got, M[rows], rtol=1e-12, atol=1e-12)
+        # each row's terms are added in input order in both: the same bits
+        assert np.array_equal(got.view(np.uint64), M[rows].view(np.uint64))
+
+
+@pytest.mark.parametrize("nthreads", [1, 3, 8])
+def test_all_cores_loop_equals_the_plain_loop_bit_for_bit(nthreads):
+    # the row-bucketed loop the CPU baseline times, against the pinned loop,
+    # on a skewed tensor with repeated coordinates and empty rows
+    dims = (50, 400, 3000)
+    idx, val = synth.random_coo(dims, 60_000, seed=21, dist="zipf", zipf_s=1.3)
+    Y = synth.random_factors(dims, 16, seed=22)
+    for d in range(3):
+        M = oracle.mttkrp(dims, idx, val, Y, d)
+        got = oracle.mttkrp_parallel(dims, idx, val, Y, d, nthreads=nthreads)
+        assert np.array_equal(got.view(np.uint64), M.view(np.uint64))
+    rowptr, perm = oracle.bucket_rows(dims, idx, 2)
+    assert rowptr[-1] == idx.shape[1] and np.array_equal(np.sort(perm), np.arange(idx.shape[1]))
+    # stable: inside a row the nonzeros keep their input order
+    for i in (0, 7, int(np.argmax(np.bincount(idx[2], minlength=dims[2])))):
+        seg = perm[rowptr[i]:rowptr[i + 1]]
+        assert np.all(np.diff(seg) > 0) and np.all(idx[2, seg] == i)
+    bad = idx.copy()
+    bad[0, 5] = dims[0]
+    with pytest.raises(ValueError):
+        oracle.mttkrp_parallel(dims, bad, val, Y, 1)
 
 
 # ---------------------------------------------------------------- Alg. 1
