@@ -20,7 +20,8 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["plan.cpp", "api.cpp"]
-HIP_SOURCES = ["ec_kernel.hip", "dr_staged.hip", "als_kernels.hip", "grad_kernel.hip", "device_plan.hip",
+HIP_SOURCES = ["ec_n4.hip", "ec_n5.hip", "ec_n6.hip", "ec_n3.hip", "ec_n8.hip", "ec_n7.hip", "ec_n2.hip",
+               "ec_kernel.hip", "dr_staged.hip", "als_kernels.hip", "grad_kernel.hip", "device_plan.hip",
                "probe.hip"]
 
 # Packed FP32 arithmetic is disabled for all device code: the compiler would

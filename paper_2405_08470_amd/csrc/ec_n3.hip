@@ -1,0 +1,11 @@
+// Instantiations of the elementwise kernel for 3-mode tensors (one
+// translation unit per mode count, so they compile in parallel).
+#include "ec_kernel.hpp"
+
+namespace spt {
+
+EcFnPtr pick_ec_n3(int rank, int fdtype, int words, int kind) {
+    return pick_layout<3>(rank, fdtype, words, kind);
+}
+
+}  // namespace spt
