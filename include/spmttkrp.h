@@ -202,6 +202,27 @@ spt_status spt_cp_gradient(spt_tensor_t t, const void *const *factors, spt_dtype
                            int32_t rank, void *const *grads, double *loss, void *stream);
 
 /*
+ * spt_mttkrp_noalloc -- spt_mttkrp for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, flags, results (bit for bit) and errors
+ * as spt_mttkrp, and it calls no hipMalloc, hipFree or other allocating
+ * routine.  Its only scratch, the partial sums of the mode's split rows
+ * (rows whose pieces lie in several partitions), lives in a fixed buffer the
+ * library holds on each device for the life of the process: 16 MiB, enough
+ * for nslots x rank x 4 bytes (nslots: carry slots of the mode); a larger
+ * need returns SPT_ERR_UNSUPPORTED with the size in spt_last_error().  The
+ * buffer needs no clearing: every slot a call reads was written earlier in
+ * that call.  All calls on one device share it, so calls that overlap on one
+ * device (other streams, other threads) race; serialise them.  Hot-row
+ * tables are used when an earlier spt_mttkrp call built them for this rank
+ * and factor type, else every factor row is read from memory (same results).
+ * No kernel timing is recorded.
+ */
+spt_status spt_mttkrp_noalloc(spt_tensor_t t, int32_t mode, const void *const *factors,
+                              spt_dtype fdtype, int32_t rank, float *out, uint32_t flags,
+                              void *stream);
+
+/*
  * spt_cp_loss -- the forward half of spt_cp_gradient: m_e at every nonzero,
  * the residual stream (kept by the handle for spt_cp_adjoint) and
  *   loss = 1/2 sum_e (x_e - m_e)^2   (device double[1], overwritten).

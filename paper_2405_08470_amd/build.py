@@ -22,7 +22,7 @@ ARCH = "gfx950"
 HOST_SOURCES = ["plan.cpp", "api.cpp"]
 HIP_SOURCES = ["ec_n4.hip", "ec_n5.hip", "ec_n6.hip", "ec_n3.hip", "ec_n8.hip", "ec_n7.hip", "ec_n2.hip",
                "ec_kernel.hip", "dr_staged.hip", "als_kernels.hip", "grad_kernel.hip", "device_plan.hip",
-               "probe.hip"]
+               "probe.hip", "noalloc.hip"]
 
 # Packed FP32 arithmetic is disabled for all device code: the compiler would
 # otherwise emit v_pk_{add,mul,fma}_f32 from plain float code.

@@ -313,16 +313,28 @@ spt_status join_side(spt_tensor_s* t, hipStream_t s) {
 // the stream rec_in, which must be in that mode's order.  With side_remap the
 // remap pass runs on the tensor's side stream after EC, and the caller must
 // call join_side() before anything on s reads rec_out.
+// With noalloc_carry != nullptr the call allocates nothing: the split-row
+// partial sums go to that buffer, hot-row tables are used only if an earlier
+// call built them for this rank and factor type, and no timing events are
+// recorded.
 spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32_t* rec_out,
                        const void* const* factors, int fdtype, int rank, float* out, hipStream_t s,
-                       bool side_remap = false) {
+                       bool side_remap = false, float* noalloc_carry = nullptr) {
     if (!spt::pick_ec_exists(t->N, rank, fdtype, t->lay.words, t->lay.kind))
         return fail(SPT_ERR_UNSUPPORTED, "no kernel compiled for this mode count / rank / record size");
+    const bool noalloc = noalloc_carry != nullptr;
     spt_status st = join_side(t, s);
-    if (st == SPT_OK) st = ensure_carry(t, rank);
     spt_tensor_s::Hot hot;
-    if (st == SPT_OK) st = ensure_hot(t, rank, fdtype, &hot);
+    if (noalloc) {
+        for (const auto& h : t->hot)
+            if (h.rank == rank && h.fdtype == fdtype) hot = h;
+    } else {
+        if (st == SPT_OK) st = ensure_carry(t, rank);
+        if (st == SPT_OK) st = ensure_hot(t, rank, fdtype, &hot);
+    }
     if (st != SPT_OK) return st;
+    float* const carry = noalloc ? noalloc_carry : t->carry;
+    auto mark_if = [&](hipStream_t on) -> hipEvent_t { return noalloc ? nullptr : mark(t, on); };
     const int N = t->N;
     // the staged pass remaps after EC when its tables exist, else EC stores
     // each record at its next position itself
@@ -336,7 +348,7 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
     a.psplit_row = t->psplit_row[mode];
     a.psplit_slot = t->psplit_slot[mode];
     a.out = out;
-    a.carry = t->carry;
+    a.carry = carry;
     a.kappa = t->kappa;
     // LDS of the hot rows: the tags of every gathered mode, then the rows
     int64_t ntag = 0, rowq = 0;
@@ -362,11 +374,11 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
     }
     const int hot_bytes = (int)((tagq + rowq) * 16);
     spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr, nullptr}, false};
-    tm.ev[0] = mark(t, s);
+    tm.ev[0] = mark_if(s);
     if (!spt::launch_ec(N, rank, fdtype, t->lay.words, t->lay.kind, t->kappa, a, hot_bytes, s))
         return fail(SPT_ERR_HIP, "launch of the elementwise kernel failed");
     HIPCHK(hipGetLastError());
-    tm.ev[1] = mark(t, s);
+    tm.ev[1] = mark_if(s);
     if (staged && side_remap) {
         spt_status st2 = ensure_side(t);
         if (st2 != SPT_OK) return st2;
@@ -374,20 +386,20 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
         HIPCHK(hipStreamWaitEvent(t->side, t->ev_fork, 0));
         spt::launch_remap_staged(t->lay.words, t->nnz, rec_in, rec_out, t->ddst[mode], t->doff[mode], t->side);
         HIPCHK(hipGetLastError());
-        tm.ev[2] = mark(t, t->side);
+        tm.ev[2] = mark_if(t->side);
         tm.side = true;
         HIPCHK(hipEventRecord(t->ev_join, t->side));
         t->join_pending = true;
     } else if (staged) {
         spt::launch_remap_staged(t->lay.words, t->nnz, rec_in, rec_out, t->ddst[mode], t->doff[mode], s);
         HIPCHK(hipGetLastError());
-        tm.ev[2] = mark(t, s);
+        tm.ev[2] = mark_if(s);
     } else {
         tm.ev[2] = tm.ev[1];
     }
     spt::FixupArgs f{};
     f.out = out;
-    f.carry = t->carry;
+    f.carry = carry;
     f.split_row = t->split_row[mode];
     f.split_ptr = t->split_ptr[mode];
     f.empty_rows = t->empty_rows[mode];
@@ -395,8 +407,8 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
     f.nempty = t->nempty[mode];
     spt::launch_fixup(rank, f, s);
     HIPCHK(hipGetLastError());
-    tm.ev[3] = mark(t, s);
-    if (t->timing && tm.ev[0] && tm.ev[1] && tm.ev[2] && tm.ev[3]) t->timed.push_back(tm);
+    tm.ev[3] = mark_if(s);
+    if (!noalloc && t->timing && tm.ev[0] && tm.ev[1] && tm.ev[2] && tm.ev[3]) t->timed.push_back(tm);
     return SPT_OK;
 }
 
@@ -830,6 +842,45 @@ spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void* const* factors, 
         if (st != SPT_OK) return st;
     }
     return run_mttkrp(t, mode, factors, fdtype, rank, out, (flags & SPT_FUSE_REMAP_NEXT) != 0, s);
+}
+
+spt_status spt_mttkrp_noalloc(spt_tensor_t t, int32_t mode, const void* const* factors, spt_dtype fdtype,
+                              int32_t rank, float* out, uint32_t flags, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(SPT_ERR_INVALID_ARG, "NULL handle");
+    if (mode < 0 || mode >= t->N) return fail(SPT_ERR_INVALID_ARG, "mode out of range");
+    if (fdtype != SPT_F32 && fdtype != SPT_BF16) return fail(SPT_ERR_UNSUPPORTED, "factor dtype not supported");
+    if (!rank_compiled(rank)) return fail(SPT_ERR_UNSUPPORTED, "rank must be 8, 16, 32, 64 or 128");
+    if (!factors || !out) return fail(SPT_ERR_INVALID_ARG, "NULL factors or out");
+    for (int w = 0; w < t->N; ++w)
+        if (w != mode && !factors[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor matrix");
+    if (flags & ~(SPT_FUSE_REMAP_NEXT | SPT_AUTO_REMAP)) return fail(SPT_ERR_INVALID_ARG, "unknown flag");
+    const int64_t need = (int64_t)t->nslots[mode] * rank * 4;
+    if (need > spt::kNoAllocScratchBytes)
+        return fail(SPT_ERR_UNSUPPORTED, "the split-row partial sums of this mode need " + std::to_string(need) +
+                                             " bytes; the fixed buffer of spt_mttkrp_noalloc holds " +
+                                             std::to_string(spt::kNoAllocScratchBytes));
+    void* scr = nullptr;
+    HIPCHK(spt::noalloc_scratch(&scr));
+    hipStream_t s = (hipStream_t)stream;
+    if (!t->copies && t->cur_mode != mode) {
+        if (!(flags & SPT_AUTO_REMAP))
+            return fail(SPT_ERR_STATE, "stream is in mode " + std::to_string(t->cur_mode) + "'s order, not " +
+                                           std::to_string(mode) + "'s");
+        spt_status st = do_remap(t, mode, s);
+        if (st != SPT_OK) return st;
+    }
+    float* carry = static_cast<float*>(scr);
+    if (t->copies) return launch_mode(t, mode, t->rec_mode[mode], nullptr, factors, fdtype, rank, out, s, false, carry);
+    const bool fuse = (flags & SPT_FUSE_REMAP_NEXT) != 0;
+    spt_status st = launch_mode(t, mode, t->rec[t->cur], fuse ? t->rec[1 - t->cur] : nullptr, factors, fdtype, rank,
+                                out, s, false, carry);
+    if (st != SPT_OK) return st;
+    if (fuse) {
+        t->cur = 1 - t->cur;
+        t->cur_mode = (mode + 1) % t->N;
+    }
+    return SPT_OK;
 }
 
 spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtype, int32_t rank,

@@ -123,6 +123,10 @@ void launch_als_finish(int rank, int nmodes, int mode, const double* Gun, const 
 void launch_scale_cols(int rank, float* Y, int64_t rows, const double* lambda, hipStream_t s);
 // dst[0..bytes) = src[0..bytes), bytes a multiple of 16 (probe.hip)
 void launch_copy_probe(const void* src, void* dst, int64_t bytes, hipStream_t s);
+// The fixed per-device buffer of spt_mttkrp_noalloc (noalloc.hip): its size,
+// and its device address on the current device (looked up once per device).
+constexpr int64_t kNoAllocScratchBytes = int64_t(16) << 20;
+hipError_t noalloc_scratch(void** ptr);
 // p[0..n) = 0 with a kernel (no memset node when a caller captures a graph)
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);
 

@@ -56,7 +56,7 @@ class spt_timing(ctypes.Structure):
 
 
 EXPORTS = ["spt_tensor_load_coo", "spt_remap_for_mode", "spt_mttkrp", "spt_cp_als_iter",
-           "spt_cp_gradient", "spt_cp_loss", "spt_cp_adjoint", "spt_copy_probe", "spt_tensor_info",
+           "spt_cp_gradient", "spt_cp_loss", "spt_cp_adjoint", "spt_copy_probe", "spt_mttkrp_noalloc", "spt_tensor_info",
            "spt_tensor_get_remap", "spt_tensor_get_records", "spt_timing_control", "spt_tensor_free",
            "spt_plan_coo", "spt_status_str", "spt_last_error"]
 
@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
     L.spt_cp_loss.argtypes = [vp, vp, i32, i32, vp, vp]
     L.spt_cp_adjoint.argtypes = [vp, vp, i32, i32, vp, vp]
     L.spt_copy_probe.argtypes = [vp, vp, i64, vp]
+    L.spt_mttkrp_noalloc.argtypes = [vp, i32, vp, i32, i32, vp, ctypes.c_uint32, vp]
     L.spt_tensor_info.argtypes = [vp, vp]
     L.spt_tensor_get_remap.argtypes = [vp, i32, vp]
     L.spt_tensor_get_records.argtypes = [vp, vp, vp, vp]
@@ -241,6 +242,24 @@ def mttkrp(t: Tensor, mode: int, factors: Sequence[Optional[torch.Tensor]], out:
         raise ValueError("out must be a contiguous CUDA float32 tensor of shape (I_mode, R)")
     _check(lib().spt_mttkrp(t.handle, int(mode), arr, BF16 if dtype == torch.bfloat16 else F32,
                             rank, out.data_ptr(), int(flags), _stream(stream)))
+    return out
+
+
+def mttkrp_noalloc(t: Tensor, mode: int, factors: Sequence[Optional[torch.Tensor]], out: torch.Tensor,
+                   flags: int = 0, stream=None) -> torch.Tensor:
+    """``mttkrp`` through the allocation-free entry point (split-row partial
+    sums in the library's fixed per-device buffer)."""
+    rank = int(out.shape[1])
+    present = [f for f in factors if f is not None]
+    dtype = present[0].dtype if present else torch.float32
+    if dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("factors must be float32 or bfloat16")
+    arr = _factor_ptrs(t, factors, rank, skip=mode, dtype=dtype)
+    if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+            and tuple(out.shape) == (t.dims[mode], rank)):
+        raise ValueError("out must be a contiguous CUDA float32 tensor of shape (I_mode, R)")
+    _check(lib().spt_mttkrp_noalloc(t.handle, int(mode), arr, BF16 if dtype == torch.bfloat16 else F32,
+                                    rank, out.data_ptr(), int(flags), _stream(stream)))
     return out
 
 

@@ -54,6 +54,7 @@ void launch_als_finish(int, int, int, const double*, const double*, double*, dou
 void launch_scale_cols(int, float*, int64_t, const double*, hipStream_t) { reached("launch_scale_cols"); }
 void launch_copy_probe(const void*, void*, int64_t, hipStream_t) { reached("launch_copy_probe"); }
 void launch_zero_i32(int32_t*, int, hipStream_t) { reached("launch_zero_i32"); }
+hipError_t noalloc_scratch(void**) { reached("noalloc_scratch"); }
 DevicePlanError build_plan_device(int, const int64_t*, int64_t, const int32_t*, const float*, const PlanOptions&,
                                   const RecordLayout&, int, hipStream_t, const DeviceAlloc&, DevicePlan*,
                                   std::string* msg) {
