@@ -170,10 +170,8 @@ bool launch_ec(int nmodes, int rank, int fdtype, int words, int kind, int kappa,
                             hot_bytes) != hipSuccess)
         return false;
     const unsigned grid = (unsigned)std::min<int64_t>(lim.cus, kappa);
-    EcArgs args = a;
-    void* params[] = {&args};
-    return hipLaunchKernel(reinterpret_cast<const void*>(f), dim3(grid), dim3(64 * kEcWaves), params,
-                           (size_t)hot_bytes, s) == hipSuccess;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(64 * kEcWaves), (size_t)hot_bytes, s, a);
+    return true;
 }
 
 void launch_fixup(int rank, const FixupArgs& a, hipStream_t s) {

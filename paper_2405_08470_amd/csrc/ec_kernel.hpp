@@ -182,7 +182,7 @@ __global__ __launch_bounds__(64 * WPB) void ec_kernel(const EcArgs a) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;
 
     // the hot rows of the gathered factors: tags, then rows
-    extern __shared__ uint4 hot_lds[];
+    HIP_DYNAMIC_SHARED(uint4, hot_lds)
 
     const int wv = threadIdx.x / 64;
     const int lane = threadIdx.x % 64;
@@ -228,9 +228,11 @@ __global__ __launch_bounds__(64 * WPB) void ec_kernel(const EcArgs a) {
         auto slot_of = [&](uint32_t row) {
             int slot = -1;
             if (sp_reg) {
-                for (int j = 0; j < nsp; ++j)
-                    if ((uint32_t)__builtin_amdgcn_readlane(my_srow, j) == row)
-                        slot = __builtin_amdgcn_readlane(my_sslot, j);
+                for (int j = 0; j < nsp; ++j) {
+                    const uint32_t r = (uint32_t)__builtin_amdgcn_readlane(my_srow, j);
+                    const int sl = __builtin_amdgcn_readlane(my_sslot, j);
+                    if (r == row) slot = sl;
+                }
             } else {
                 slot = split_slot(a, sp0, sp1, (int)row);
             }
@@ -294,8 +296,10 @@ __global__ __launch_bounds__(64 * WPB) void ec_kernel(const EcArgs a) {
 #pragma unroll
                 for (int k = 0; k < N; ++k) mine.w[k] = pick_word(dec, a.rot[k]);
                 mine.w[N] = rword<RW - 1, RW>(cur);
-                mine.w[N + 1] = (uint32_t)slot_of(mine.w[0]);
             }
+            // every lane (the lookup reads other lanes); lanes past the
+            // group's range look up a stale row and never use it
+            mine.w[N + 1] = (uint32_t)slot_of(mine.w[0]);
             const int cnt = gn - step0;
 #pragma unroll
             for (int kb = 0; kb < L; kb += B) {
