@@ -60,7 +60,7 @@ def log(*a):
 CSRC = "paper_2405_08470_amd/csrc/"
 # kernel family -> sources the kernel is built from (for the profile match)
 SOURCES = {
-    "ec_kernel": (CSRC + "ec_kernel.hip", CSRC + "kernels.hpp"),
+    "ec_kernel": (CSRC + "ec_kernel.hpp", CSRC + "ec_kernel.hip", CSRC + "kernels.hpp"),
     "remap_flat_kernel": (CSRC + "dr_staged.hip", CSRC + "kernels.hpp"),
 }
 
@@ -231,7 +231,7 @@ def run_workload(torch, S, synth, name, K, W, args, headline=False):
     if headline:
         # the dominant kernel of the pass and its roofline
         if sum(rm) > sum(ec):
-            kernel = f"remap_flat_kernel<{rec // 4}, {S.stage_chunk(rec)}>"
+            kernel = f"remap_flat_kernel<{rec // 4}>"
             dom_bytes, dom_ms = b_rm, sum(rm) / N
         else:
             kernel = f"ec_kernel<{N}, {R}, {rec // 4}>"

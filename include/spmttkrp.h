@@ -65,10 +65,11 @@ typedef struct spt_opts {
     int32_t dr;         /* how a remapping MTTKRP moves the stream to the next
                            mode's order (Alg. 3), copies == 0 only:
                            0 = a second pass after the elementwise kernel
-                           that writes each chunk of 4096 consecutive
-                           records (16-byte records; 2048 / 1024 for 32 / 48
-                           bytes) in destination order; the load builds its
-                           tables, 6 bytes per nonzero and mode.  1 = fused: the elementwise kernel stores
+                           that writes each chunk of 65536 consecutive
+                           records (16-byte records; 32768 / 16384 for 32 /
+                           48 bytes; spt_info.remap_chunk) in destination
+                           order; the load builds its tables, 6 bytes per
+                           nonzero and mode.  1 = fused: the elementwise kernel stores
                            every record at its next position.  The next
                            stream is identical either way                   */
     int32_t layout;     /* record layout of the stream (Sec. 3.5): 0 = chosen
@@ -98,6 +99,10 @@ typedef struct spt_info {
     double norm_sq;          /* ||X||_F^2 with repeated coordinates summed   */
     double prep_seconds;     /* wall time of the load (preprocessing + upload) */
     int64_t device_bytes;    /* device memory held by the handle             */
+    int32_t remap_chunk;     /* records per chunk of the remap pass (each
+                                chunk written in destination order); 0 when
+                                the handle has no remap pass (opts.dr = 1 or
+                                one copy per mode)                           */
 } spt_info;
 
 /* mttkrp flags */

@@ -537,15 +537,33 @@ namespace {
 // the tables depend only on nxt_d, so they are identical either way).
 spt_status build_stage_tables(spt_tensor_s* t, hipStream_t s) {
     if (t->copies || t->dr != 0) return SPT_OK;
-    for (int d = 0; d < t->N; ++d) {
-        spt_status st = dalloc(t, &t->ddst[d], (size_t)t->nnz, &t->allocs);
-        if (st == SPT_OK) st = dalloc(t, &t->doff[d], (size_t)t->nnz, &t->allocs);
-        if (st != SPT_OK) return st;
-        spt::launch_stage_tables(t->lay.words, t->nxt[d], t->nnz, t->ddst[d], t->doff[d], s);
-        HIPCHK(hipGetLastError());
+    // the sorted runs before the merge into whole chunks (freed on return)
+    std::vector<void*> temps;
+    int32_t* tmp_dst = nullptr;
+    uint16_t* tmp_off = nullptr;
+    spt_status st = SPT_OK;
+    const int64_t bytes_before = t->device_bytes;
+    if (spt::stage_tables_need_temp(t->lay.words)) {
+        st = dalloc(t, &tmp_dst, (size_t)t->nnz, &temps);
+        if (st == SPT_OK) st = dalloc(t, &tmp_off, (size_t)t->nnz, &temps);
     }
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(SPT_ERR_HIP, "hipStreamSynchronize after the remap tables");
-    return SPT_OK;
+    const int64_t temp_bytes = t->device_bytes - bytes_before;
+    auto free_temps = [&]() {
+        for (void* p : temps) (void)hipFree(p);
+        t->device_bytes -= temp_bytes;
+    };
+    for (int d = 0; d < t->N && st == SPT_OK; ++d) {
+        st = dalloc(t, &t->ddst[d], (size_t)t->nnz, &t->allocs);
+        if (st == SPT_OK) st = dalloc(t, &t->doff[d], (size_t)t->nnz, &t->allocs);
+        if (st != SPT_OK) break;
+        spt::launch_stage_tables(t->lay.words, t->nxt[d], t->nnz, t->ddst[d], t->doff[d], tmp_dst, tmp_off, s);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = hip_fail(e, "launch of the remap table kernels");
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && st == SPT_OK)
+        st = fail(SPT_ERR_HIP, "hipStreamSynchronize after the remap tables");
+    free_temps();
+    return st;
 }
 
 // The load with the device planner: streams and next positions are built in
@@ -812,6 +830,7 @@ spt_status spt_tensor_info(spt_tensor_t t, spt_info* info) {
     info->norm_sq = t->norm_sq;
     info->prep_seconds = t->prep_seconds;
     info->device_bytes = t->device_bytes;
+    info->remap_chunk = t->ddst[0] ? spt::stage_chunk(t->lay.words) : 0;
     return SPT_OK;
 }
 

@@ -3,19 +3,24 @@
 //
 // The fused form stores each record at its next-mode position while the
 // elementwise computation runs (one 16-byte store to a random address per
-// nonzero).  Here the stream is cut into chunks of C consecutive records, and
-// the records of each chunk are written in the order of their destinations:
-// consecutive threads take consecutive table slots, so records of one chunk
-// that land next to each other in the next mode's stream go out in the same
-// store instruction and share memory transactions.  Each chunk (64 KB of
-// records) is read in that order too; all workgroups of a chunk run on one XCD,
-// so its lines are fetched once into that XCD's L2 and then hit there.  The next mode's stream is the same as the fused form's, bit for bit.
+// nonzero).  Here the stream is cut into chunks of C consecutive records (1 MB
+// of records: 65536 16-byte records), and the records of each chunk are
+// written in the order of their destinations: consecutive threads take
+// consecutive table slots, so records of one chunk that land next to each
+// other in the next mode's stream go out in the same store instruction and
+// share cache lines.  In the next mode's order the records one source
+// partition sends to one row are consecutive, so the longer the chunk, the
+// longer these runs and the fewer lines the pass writes partially.  Each
+// chunk is read in destination order too; all workgroups of a chunk run on one
+// XCD, so its lines are fetched once into that XCD's L2 and then hit there.
+// The next mode's stream is the same as the fused form's, bit for bit.
 //
 // Tables (built once at load, per mode d, from the next positions nxt_d):
 //   ddst[c*C + j] = j-th smallest destination among the records of chunk c
 //   doff[c*C + j] = offset inside chunk c of the record that goes there
 // Destinations are distinct (nxt_d is a permutation), so the sorted order is
-// unique and does not depend on how it is computed.
+// unique and does not depend on how it is computed: sub-runs of kSub records
+// are sorted in LDS, then each chunk's sub-runs are merged by rank.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -23,10 +28,10 @@
 
 #include "kernels.hpp"
 
-// Records per chunk for 16-byte records (32-byte: half, 48-byte: a quarter);
-// a power of two.
-#ifndef SPT_STAGE_CHUNK16
-#define SPT_STAGE_CHUNK16 4096
+// Bytes of records per chunk (the chunk holds the largest power of two of
+// records that fits, at least kSub and at most 65536 so offsets fit 16 bits).
+#ifndef SPT_STAGE_CHUNK_BYTES
+#define SPT_STAGE_CHUNK_BYTES (1 << 20)
 #endif
 
 namespace spt {
@@ -34,10 +39,10 @@ namespace {
 
 constexpr int kStageThreads = 256;  // table sort
 constexpr int kRemapThreads = 256;
-constexpr int kChunk16 = SPT_STAGE_CHUNK16;
-static_assert((kChunk16 & (kChunk16 - 1)) == 0 && kChunk16 >= 1024 && kChunk16 <= 16384, "chunk");
+constexpr int kSub = 4096;           // entries sorted in LDS by one workgroup
 
-// One workgroup per chunk: bitonic sort of (destination, offset) pairs in LDS.
+// One workgroup per run of C consecutive entries: bitonic sort of (destination,
+// offset) pairs in LDS.
 template <int C>
 __global__ __launch_bounds__(kStageThreads) void stage_tables_kernel(const int32_t* __restrict__ nxt,
                                                                       int64_t nnz, int32_t* __restrict__ ddst,
@@ -76,22 +81,51 @@ __global__ __launch_bounds__(kStageThreads) void stage_tables_kernel(const int32
     }
 }
 
+// Merge of the sorted sub-runs of each chunk of 2^cshift entries: an entry's
+// place in its chunk is its place in its own sub-run plus the number of
+// smaller destinations in the chunk's other sub-runs (binary searches;
+// destinations are distinct).  Offsets become offsets inside the chunk.
+__global__ __launch_bounds__(kStageThreads) void merge_runs_kernel(const int32_t* __restrict__ sdst,
+                                                                   const uint16_t* __restrict__ soff,
+                                                                   int64_t nnz, int cshift,
+                                                                   int32_t* __restrict__ ddst,
+                                                                   uint16_t* __restrict__ doff) {
+    const int64_t i = blockIdx.x * (int64_t)kStageThreads + threadIdx.x;
+    if (i >= nnz) return;
+    const int64_t c0 = (i >> cshift) << cshift;
+    const int64_t r0 = (i / kSub) * kSub;
+    const int64_t cend = (c0 + (int64_t(1) << cshift)) < nnz ? c0 + (int64_t(1) << cshift) : nnz;
+    const int32_t key = sdst[i];
+    int64_t pos = i - r0;
+    for (int64_t rs = c0; rs < cend; rs += kSub) {
+        if (rs == r0) continue;
+        int64_t lo = rs, hi = (rs + kSub) < cend ? rs + kSub : cend;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sdst[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        pos += lo - rs;
+    }
+    ddst[c0 + pos] = key;
+    doff[c0 + pos] = (uint16_t)((r0 - c0) + soff[i]);
+}
+
 // One record per thread: slot j of the tables, read from its chunk in L2.
-template <int RW, int C>
+template <int RW>
 __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_t* __restrict__ in,
                                                                     uint32_t* __restrict__ out,
                                                                     const int32_t* __restrict__ ddst,
                                                                     const uint16_t* __restrict__ doff,
-                                                                    int64_t nnz) {
+                                                                    int64_t nnz, int cshift) {
     constexpr int Q = RW / 4;
     // the grid is a multiple of 8 chunks; block b runs on XCD b % 8 and takes
     // the (b / 8)-th block of that XCD's chunks c = x, x + 8, x + 16, ...
-    constexpr unsigned BPC = C / kRemapThreads;  // workgroups per chunk
+    const unsigned bpc = 1u << (cshift - 8);  // workgroups per chunk
     const unsigned b = blockIdx.x, x = b % 8u, r = b / 8u;
-    const unsigned v = ((r / BPC) * 8u + x) * BPC + r % BPC;
+    const unsigned v = ((r / bpc) * 8u + x) * bpc + r % bpc;
     const int64_t j = (int64_t)v * kRemapThreads + threadIdx.x;
     if (j >= nnz) return;
-    const int64_t p = (j / C) * C + doff[j];
+    const int64_t p = ((j >> cshift) << cshift) + doff[j];
     const int64_t q = ddst[j];
     const uint4* src = reinterpret_cast<const uint4*>(in);
     uint4* dst = reinterpret_cast<uint4*>(out);
@@ -99,44 +133,48 @@ __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_
     for (int w = 0; w < Q; ++w) dst[q * Q + w] = src[p * Q + w];
 }
 
+int chunk_shift(int words) {
+    int sh = 16;
+    while (sh > 12 && ((int64_t(1) << sh) * words * 4 > (int64_t)SPT_STAGE_CHUNK_BYTES)) --sh;
+    return sh;
+}
+
 }  // namespace
 
-int stage_chunk(int words) {
-    // 64 KB of LDS per workgroup at most; a power of two for the bitonic sort
-    return words == 4 ? kChunk16 : words == 8 ? kChunk16 / 2 : kChunk16 / 4;
-}
+int stage_chunk(int words) { return 1 << chunk_shift(words); }
 
 void launch_stage_tables(int words, const int32_t* nxt, int64_t nnz, int32_t* ddst, uint16_t* doff,
-                         hipStream_t s) {
+                         int32_t* tmp_dst, uint16_t* tmp_off, hipStream_t s) {
     if (nnz == 0) return;
-    const int C = stage_chunk(words);
-    const unsigned blocks = (unsigned)((nnz + C - 1) / C);
-    if (C == kChunk16)
-        hipLaunchKernelGGL(stage_tables_kernel<kChunk16>, dim3(blocks), dim3(kStageThreads), 0, s, nxt, nnz, ddst,
-                           doff);
-    else if (C == kChunk16 / 2)
-        hipLaunchKernelGGL(stage_tables_kernel<kChunk16 / 2>, dim3(blocks), dim3(kStageThreads), 0, s, nxt, nnz,
-                           ddst, doff);
-    else
-        hipLaunchKernelGGL(stage_tables_kernel<kChunk16 / 4>, dim3(blocks), dim3(kStageThreads), 0, s, nxt, nnz,
-                           ddst, doff);
+    const int cshift = chunk_shift(words);
+    const bool merge = (1 << cshift) > kSub;
+    const unsigned subs = (unsigned)((nnz + kSub - 1) / kSub);
+    hipLaunchKernelGGL(stage_tables_kernel<kSub>, dim3(subs), dim3(kStageThreads), 0, s, nxt, nnz,
+                       merge ? tmp_dst : ddst, merge ? tmp_off : doff);
+    if (merge) {
+        const unsigned blocks = (unsigned)((nnz + kStageThreads - 1) / kStageThreads);
+        hipLaunchKernelGGL(merge_runs_kernel, dim3(blocks), dim3(kStageThreads), 0, s, (const int32_t*)tmp_dst,
+                           (const uint16_t*)tmp_off, nnz, cshift, ddst, doff);
+    }
 }
+
+bool stage_tables_need_temp(int words) { return (1 << chunk_shift(words)) > kSub; }
 
 void launch_remap_staged(int words, int64_t nnz, const uint32_t* in, uint32_t* out, const int32_t* ddst,
                          const uint16_t* doff, hipStream_t s) {
     if (nnz == 0) return;
-    const int C = stage_chunk(words);
-    const int64_t nchunks = (nnz + C - 1) / C;
-    const unsigned blocks = (unsigned)(((nchunks + 7) / 8) * 8 * (C / kRemapThreads));
+    const int cshift = chunk_shift(words);
+    const int64_t nchunks = (nnz + (int64_t(1) << cshift) - 1) >> cshift;
+    const unsigned blocks = (unsigned)(((nchunks + 7) / 8) * 8 * ((int64_t(1) << cshift) / kRemapThreads));
     if (words == 4)
-        hipLaunchKernelGGL((remap_flat_kernel<4, kChunk16>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out,
-                           ddst, doff, nnz);
+        hipLaunchKernelGGL((remap_flat_kernel<4>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out, ddst, doff,
+                           nnz, cshift);
     else if (words == 8)
-        hipLaunchKernelGGL((remap_flat_kernel<8, kChunk16 / 2>), dim3(blocks), dim3(kRemapThreads), 0, s, in,
-                           out, ddst, doff, nnz);
+        hipLaunchKernelGGL((remap_flat_kernel<8>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out, ddst, doff,
+                           nnz, cshift);
     else
-        hipLaunchKernelGGL((remap_flat_kernel<12, kChunk16 / 4>), dim3(blocks), dim3(kRemapThreads), 0, s, in,
-                           out, ddst, doff, nnz);
+        hipLaunchKernelGGL((remap_flat_kernel<12>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out, ddst, doff,
+                           nnz, cshift);
 }
 
 }  // namespace spt

@@ -170,7 +170,7 @@ bool launch_ec(int nmodes, int rank, int fdtype, int words, int kind, int kappa,
                             hot_bytes) != hipSuccess)
         return false;
     const unsigned grid = (unsigned)std::min<int64_t>(lim.cus, kappa);
-    hipLaunchKernelGGL(f, dim3(grid), dim3(64 * kEcWaves), (size_t)hot_bytes, s, a);
+    hipLaunchKernelGGL(f, dim3(grid), dim3(64 * ec_waves(nmodes, rank, fdtype ? 2 : 4)), (size_t)hot_bytes, s, a);
     return true;
 }
 

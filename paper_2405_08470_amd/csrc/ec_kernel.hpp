@@ -457,26 +457,24 @@ __global__ __launch_bounds__(64 * WPB) void ec_kernel(const EcArgs a) {
 
 using EcFn = EcFnPtr;
 
-constexpr int kWaves = kEcWaves;
-
 template <int N, int RW, int KIND>
 EcFn pick_rank(int rank, int fdtype) {
     if (fdtype == 0) {
         switch (rank) {
-            case 8: return ec_kernel<N, 8, RW, KIND, FacF32, kWaves>;
-            case 16: return ec_kernel<N, 16, RW, KIND, FacF32, kWaves>;
-            case 32: return ec_kernel<N, 32, RW, KIND, FacF32, kWaves>;
-            case 64: return ec_kernel<N, 64, RW, KIND, FacF32, kWaves>;
-            case 128: return ec_kernel<N, 128, RW, KIND, FacF32, kWaves>;
+            case 8: return ec_kernel<N, 8, RW, KIND, FacF32, ec_waves(N, 8, 4)>;
+            case 16: return ec_kernel<N, 16, RW, KIND, FacF32, ec_waves(N, 16, 4)>;
+            case 32: return ec_kernel<N, 32, RW, KIND, FacF32, ec_waves(N, 32, 4)>;
+            case 64: return ec_kernel<N, 64, RW, KIND, FacF32, ec_waves(N, 64, 4)>;
+            case 128: return ec_kernel<N, 128, RW, KIND, FacF32, ec_waves(N, 128, 4)>;
             default: return nullptr;
         }
     }
     switch (rank) {
-        case 8: return ec_kernel<N, 8, RW, KIND, FacBF16, kWaves>;
-        case 16: return ec_kernel<N, 16, RW, KIND, FacBF16, kWaves>;
-        case 32: return ec_kernel<N, 32, RW, KIND, FacBF16, kWaves>;
-        case 64: return ec_kernel<N, 64, RW, KIND, FacBF16, kWaves>;
-        case 128: return ec_kernel<N, 128, RW, KIND, FacBF16, kWaves>;
+        case 8: return ec_kernel<N, 8, RW, KIND, FacBF16, ec_waves(N, 8, 2)>;
+        case 16: return ec_kernel<N, 16, RW, KIND, FacBF16, ec_waves(N, 16, 2)>;
+        case 32: return ec_kernel<N, 32, RW, KIND, FacBF16, ec_waves(N, 32, 2)>;
+        case 64: return ec_kernel<N, 64, RW, KIND, FacBF16, ec_waves(N, 64, 2)>;
+        case 128: return ec_kernel<N, 128, RW, KIND, FacBF16, ec_waves(N, 128, 2)>;
         default: return nullptr;
     }
 }

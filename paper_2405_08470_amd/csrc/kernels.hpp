@@ -39,11 +39,21 @@ struct EcArgs {
 };
 
 // Waves per workgroup of the elementwise kernel (one workgroup per CU, all
-// of the CU's LDS for hot factor rows).
+// of the CU's LDS for hot factor rows): SPT_EC_WAVES when a nonzero's gathered
+// rows are at most SPT_EC_WIDE_BYTES bytes per lane group (the kernel's
+// registers then allow that many waves), else SPT_EC_WAVES_WIDE.
 #ifndef SPT_EC_WAVES
 #define SPT_EC_WAVES 8
 #endif
-constexpr int kEcWaves = SPT_EC_WAVES;
+#ifndef SPT_EC_WAVES_WIDE
+#define SPT_EC_WAVES_WIDE 8
+#endif
+#ifndef SPT_EC_WIDE_BYTES
+#define SPT_EC_WIDE_BYTES 768
+#endif
+constexpr int ec_waves(int nmodes, int rank, int fbytes) {
+    return (nmodes - 1) * rank * fbytes <= SPT_EC_WIDE_BYTES ? SPT_EC_WAVES : SPT_EC_WAVES_WIDE;
+}
 
 // Forward pass of the gradient fit (grad_kernel.hip).
 struct ForwardArgs {
@@ -70,8 +80,8 @@ using EcFnPtr = void (*)(EcArgs);
 
 // fdtype 0: FP32 factors, 1: BF16 factors.  Returns false if the combination
 // (nmodes, rank, factor type, record words, layout kind) has no kernel or the
-// launch failed.  One workgroup of kEcWaves waves per CU (at most kappa);
-// each wave takes partitions block + grid * (wave + kEcWaves j).  hot_bytes: the dynamic LDS
+// launch failed.  One workgroup of W = ec_waves(...) waves per CU (at most kappa);
+// each wave takes partitions block + grid * (wave + W j).  hot_bytes: the dynamic LDS
 // of the hot-row tables (at most ec_hot_lds_bytes(...)).
 bool launch_ec(int nmodes, int rank, int fdtype, int words, int kind, int kappa, const EcArgs& a,
                int hot_bytes, hipStream_t s);
@@ -93,9 +103,12 @@ void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,
 // Staged remapping (dr_staged.hip): records in chunks of stage_chunk(words)
 // consecutive stream positions; per chunk, the destinations in increasing
 // order (ddst) and the offset inside the chunk of the record for each (doff).
+// When stage_tables_need_temp(words), the build needs nnz-entry temporaries
+// tmp_dst / tmp_off (otherwise they may be null).
 int stage_chunk(int words);
+bool stage_tables_need_temp(int words);
 void launch_stage_tables(int words, const int32_t* nxt, int64_t nnz, int32_t* ddst, uint16_t* doff,
-                         hipStream_t s);
+                         int32_t* tmp_dst, uint16_t* tmp_off, hipStream_t s);
 // out[ddst[j]] = in[chunk(j) * C + doff[j]] for every j < nnz
 void launch_remap_staged(int words, int64_t nnz, const uint32_t* in, uint32_t* out, const int32_t* ddst,
                          const uint16_t* doff, hipStream_t s);

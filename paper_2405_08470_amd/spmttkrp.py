@@ -46,7 +46,7 @@ class spt_info(ctypes.Structure):
                 ("nnz", ctypes.c_int64), ("dims", ctypes.c_int64 * 8),
                 ("max_load", ctypes.c_int64 * 8), ("split_rows", ctypes.c_int64 * 8),
                 ("norm_sq", ctypes.c_double), ("prep_seconds", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("remap_chunk", ctypes.c_int32)]
 
 
 class spt_timing(ctypes.Structure):
@@ -358,8 +358,9 @@ def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
 
 
 def stage_chunk(record_bytes: int) -> int:
-    """Records per chunk of the staged remap (opts.dr = 0) for a record size."""
-    return {16: 4096, 32: 2048, 48: 1024}[int(record_bytes)]
+    """Records per chunk of the staged remap (opts.dr = 0) for a record size
+    (what spt_info.remap_chunk reports for a handle with that record size)."""
+    return {16: 65536, 32: 32768, 48: 16384}[int(record_bytes)]
 
 
 def tensor_info(t: Tensor) -> Dict[str, object]:
@@ -369,7 +370,7 @@ def tensor_info(t: Tensor) -> Dict[str, object]:
     return {"nmodes": N, "cur_mode": i.cur_mode, "kappa": i.kappa, "record_bytes": i.record_bytes,
             "nnz": i.nnz, "dims": list(i.dims[:N]), "max_load": list(i.max_load[:N]),
             "split_rows": list(i.split_rows[:N]), "norm_sq": i.norm_sq,
-            "prep_seconds": i.prep_seconds, "device_bytes": i.device_bytes}
+            "prep_seconds": i.prep_seconds, "device_bytes": i.device_bytes, "remap_chunk": i.remap_chunk}
 
 
 def tensor_get_remap(t: Tensor, mode: int) -> np.ndarray:

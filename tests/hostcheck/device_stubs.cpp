@@ -31,7 +31,8 @@ void launch_remap(int, int64_t, const uint32_t*, uint32_t*, const int32_t* const
     reached("launch_remap");
 }
 int stage_chunk(int) { reached("stage_chunk"); }
-void launch_stage_tables(int, const int32_t*, int64_t, int32_t*, uint16_t*, hipStream_t) {
+bool stage_tables_need_temp(int) { reached("stage_tables_need_temp"); }
+void launch_stage_tables(int, const int32_t*, int64_t, int32_t*, uint16_t*, int32_t*, uint16_t*, hipStream_t) {
     reached("launch_stage_tables");
 }
 void launch_remap_staged(int, int64_t, const uint32_t*, uint32_t*, const int32_t*, const uint16_t*, hipStream_t) {

@@ -116,4 +116,31 @@ def test_options_reserved_words_must_be_zero_and_remap_forms_map():
     assert [S._opts(0, None, 0, layout=k).layout for k in ("auto", "word32", "half16", "packed")] == [0, 1, 2, 3]
     with pytest.raises(ValueError):
         S._opts(0, None, 0, layout="soa")
-    assert [S.stage_chunk(b) for b in (16, 32, 48)] == [4096, 2048, 1024]
+    assert [S.stage_chunk(b) for b in (16, 32, 48)] == [65536, 32768, 16384]
+
+
+def test_struct_layouts_of_the_binding_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C sizes and field
+    offsets (a struct that grew in the header and not in a mirror would be
+    written past its end)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    mirrors = {"spt_info": S.spt_info, "spt_opts": S.spt_opts, "spt_timing": S.spt_timing}
+    src = ["#include <stddef.h>", "#include <stdio.h>", "#include \"spmttkrp.h\"", "int main(void) {"]
+    for name, cls in mirrors.items():
+        src.append(f'    printf("{name} %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            src.append(f'    printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    src.append("    return 0;\n}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in mirrors.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, f"{name}.{f[0]}"

@@ -76,17 +76,9 @@ def lib(tmp_path_factory):
     shutil.rmtree(out, ignore_errors=True)
 
 
-class Opts(ctypes.Structure):
-    _fields_ = [("kappa", ctypes.c_int32), ("copies", ctypes.c_int32), ("split_cap", ctypes.c_int64),
-                ("prep", ctypes.c_int32), ("dr", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
-
-
-class Info(ctypes.Structure):
-    _fields_ = [("nmodes", ctypes.c_int32), ("cur_mode", ctypes.c_int32), ("kappa", ctypes.c_int32),
-                ("record_bytes", ctypes.c_int32), ("nnz", ctypes.c_int64), ("dims", ctypes.c_int64 * 8),
-                ("max_load", ctypes.c_int64 * 8), ("split_rows", ctypes.c_int64 * 8),
-                ("norm_sq", ctypes.c_double), ("prep_seconds", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+# the binding's mirrors of the header's structs (their layout is checked
+# against the header in test_abi)
+from paper_2405_08470_amd.spmttkrp import spt_info as Info, spt_opts as Opts  # noqa: E402
 
 
 class T:
@@ -149,6 +141,8 @@ CASES = [
     ("zipf2_nosplit", (500, 400), 15_000, "zipf", 1.5, 16, 31, 0),
     ("zipf8_r16", (9, 8, 7, 6, 5, 4, 3, 2), 4_000, "zipf", 1.1, 16, 5, None),
     ("uniform3_r16", (60, 50, 40), 8_000, "uniform", 1.1, 16, 0, None),
+    # more than two remap chunks of 65536 records, the last one partial
+    ("zipf3_chunks", (400, 300, 2000), 140_000, "zipf", 1.1, 8, 0, None),
 ]
 
 

@@ -34,7 +34,7 @@ def _build(tmp_path, name, old, new):
     path = tmp_path / f"{name}.c"
     path.write_text(src.replace(old, new, 1))
     so = tmp_path / f"lib{name}.so"
-    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(so), str(path)])
+    subprocess.check_call(["gcc", "-O1", "-fopenmp", "-shared", "-fPIC", "-o", str(so), str(path)])
     return str(so)
 
 
