@@ -70,14 +70,6 @@ struct spt_tensor_s {
     uint16_t* doff[8] = {};
     int32_t nsplit[8] = {}, nslots[8] = {}, nempty[8] = {};
     int64_t max_load[8] = {};
-    std::vector<int32_t> hot_rows[8];  // rows of degree >= 2, hottest first (planner)
-    // hot-row tables of the elementwise kernel, per (rank, factor type)
-    struct Hot {
-        int rank = 0, fdtype = -1;
-        int h[8] = {}, full[8] = {};
-        int32_t* tag[8] = {};  // device, h[w] entries (not for full modes)
-    };
-    std::vector<Hot> hot;
     std::vector<int32_t> order0;  // input nonzero at each mode-0 position
     double norm_sq = 0.0;
     double prep_seconds = 0.0;
@@ -211,75 +203,6 @@ spt_status ensure_carry(spt_tensor_s* t, int rank) {
     return SPT_OK;
 }
 
-// Slot of row c in a direct-mapped table of h slots (the kernel's hash).
-uint32_t hot_slot_host(uint32_t c, uint32_t h) {
-    return (uint32_t)(((uint64_t)(uint32_t)(c * 0x9E3779B1u) * h) >> 32);
-}
-
-// The hot-row tables for (rank, fdtype): how many rows of each mode the
-// elementwise kernel keeps in LDS and, for modes not kept whole, which row
-// each slot holds.  Every mode gets the same share (rows), a mode whose rows
-// all fit that share is kept whole, and the share is the largest for which
-// the modes gathered by any launch fit the LDS the kernel leaves free.
-spt_status ensure_hot(spt_tensor_s* t, int rank, int fdtype, spt_tensor_s::Hot* out) {
-    for (const auto& h : t->hot)
-        if (h.rank == rank && h.fdtype == fdtype) {
-            *out = h;
-            return SPT_OK;
-        }
-    const int N = t->N;
-    spt_tensor_s::Hot hc;
-    hc.rank = rank;
-    hc.fdtype = fdtype;
-    const int budget = spt::ec_hot_lds_bytes(N, rank, fdtype, t->lay.words, t->lay.kind);
-    if (budget < 0) return fail(SPT_ERR_HIP, "device query for the elementwise kernel failed");
-    const int64_t rb = (int64_t)rank * (fdtype ? 2 : 4);
-    auto layout_for = [&](int64_t lam, int64_t* h, int* full) {
-        for (int w = 0; w < N; ++w) {
-            full[w] = t->dims[w] <= lam ? 1 : 0;
-            h[w] = full[w] ? t->dims[w] : std::min<int64_t>(lam, (int64_t)t->hot_rows[w].size());
-        }
-    };
-    auto fits = [&](int64_t lam) {
-        int64_t h[8];
-        int full[8];
-        layout_for(lam, h, full);
-        for (int d = 0; d < N; ++d) {
-            int64_t tagb = 0, rowb = 0;
-            for (int w = 0; w < N; ++w) {
-                if (w == d) continue;
-                tagb += full[w] ? 0 : 4 * h[w];
-                rowb += h[w] * rb;
-            }
-            if ((tagb + 15) / 16 * 16 + rowb > budget) return false;
-        }
-        return true;
-    };
-    int64_t lo = 0, hi = 1;
-    for (int w = 0; w < N; ++w) hi = std::max<int64_t>(hi, t->dims[w]);
-    while (lo < hi) {  // the largest share that fits
-        const int64_t mid = lo + (hi - lo + 1) / 2;
-        if (fits(mid)) lo = mid; else hi = mid - 1;
-    }
-    int64_t h64[8];
-    layout_for(lo, h64, hc.full);
-    for (int w = 0; w < N; ++w) {
-        hc.h[w] = (int)h64[w];
-        if (hc.full[w] || hc.h[w] == 0) continue;
-        std::vector<int32_t> tag((size_t)hc.h[w], -1);
-        for (int32_t row : t->hot_rows[w]) {  // hottest first: a slot keeps its hottest row
-            const uint32_t sl = hot_slot_host((uint32_t)row, (uint32_t)hc.h[w]);
-            if (tag[sl] < 0) tag[sl] = row;
-        }
-        spt_status st = dalloc(t, &hc.tag[w], tag.size(), &t->allocs);
-        if (st != SPT_OK) return st;
-        HIPCHK(hipMemcpy(hc.tag[w], tag.data(), tag.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
-    t->hot.push_back(hc);
-    *out = hc;
-    return SPT_OK;
-}
-
 // An event recorded on `s` now (timing only); nullptr if timing is off.
 hipEvent_t mark(spt_tensor_s* t, hipStream_t s) {
     if (!t->timing) return nullptr;
@@ -314,9 +237,7 @@ spt_status join_side(spt_tensor_s* t, hipStream_t s) {
 // remap pass runs on the tensor's side stream after EC, and the caller must
 // call join_side() before anything on s reads rec_out.
 // With noalloc_carry != nullptr the call allocates nothing: the split-row
-// partial sums go to that buffer, hot-row tables are used only if an earlier
-// call built them for this rank and factor type, and no timing events are
-// recorded.
+// partial sums go to that buffer and no timing events are recorded.
 spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32_t* rec_out,
                        const void* const* factors, int fdtype, int rank, float* out, hipStream_t s,
                        bool side_remap = false, float* noalloc_carry = nullptr) {
@@ -324,14 +245,7 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
         return fail(SPT_ERR_UNSUPPORTED, "no kernel compiled for this mode count / rank / record size");
     const bool noalloc = noalloc_carry != nullptr;
     spt_status st = join_side(t, s);
-    spt_tensor_s::Hot hot;
-    if (noalloc) {
-        for (const auto& h : t->hot)
-            if (h.rank == rank && h.fdtype == fdtype) hot = h;
-    } else {
-        if (st == SPT_OK) st = ensure_carry(t, rank);
-        if (st == SPT_OK) st = ensure_hot(t, rank, fdtype, &hot);
-    }
+    if (st == SPT_OK && !noalloc) st = ensure_carry(t, rank);
     if (st != SPT_OK) return st;
     float* const carry = noalloc ? noalloc_carry : t->carry;
     auto mark_if = [&](hipStream_t on) -> hipEvent_t { return noalloc ? nullptr : mark(t, on); };
@@ -349,33 +263,16 @@ spt_status launch_mode(spt_tensor_s* t, int mode, const uint32_t* rec_in, uint32
     a.psplit_slot = t->psplit_slot[mode];
     a.out = out;
     a.carry = carry;
-    a.kappa = t->kappa;
-    // LDS of the hot rows: the tags of every gathered mode, then the rows
-    int64_t ntag = 0, rowq = 0;
     for (int k = 0; k < N; ++k) {
         const int w = (mode + k) % N;
         a.fac[k] = factors[w];
         a.rot[k] = w;
         a.foff[k] = t->lay.off[k];
         a.fmask[k] = (uint32_t)((uint64_t(1) << t->lay.bits[k]) - 1);
-        if (k > 0) {
-            a.hot_h[k] = hot.h[w];
-            a.hot_full[k] = hot.full[w];
-            a.hot_tag[k] = hot.tag[w];
-            a.hot_tag_off[k] = (int32_t)ntag;
-            ntag += hot.full[w] ? 0 : hot.h[w];
-        }
     }
-    const int64_t tagq = (ntag * 4 + 15) / 16;
-    for (int k = 1; k < N; ++k) {
-        const int w = (mode + k) % N;
-        a.hot_row_off[k] = (int32_t)(tagq + rowq);
-        rowq += (int64_t)hot.h[w] * rank * (fdtype ? 2 : 4) / 16;
-    }
-    const int hot_bytes = (int)((tagq + rowq) * 16);
     spt_tensor_s::Timed tm{mode, {nullptr, nullptr, nullptr, nullptr, nullptr}, false};
     tm.ev[0] = mark_if(s);
-    if (!spt::launch_ec(N, rank, fdtype, t->lay.words, t->lay.kind, t->kappa, a, hot_bytes, s))
+    if (!spt::launch_ec(N, rank, fdtype, t->lay.words, t->lay.kind, t->kappa, a, s))
         return fail(SPT_ERR_HIP, "launch of the elementwise kernel failed");
     HIPCHK(hipGetLastError());
     tm.ev[1] = mark_if(s);
@@ -610,7 +507,6 @@ spt_status load_device(int32_t nmodes, const int64_t* dims, int64_t nnz, const i
             t->nslots[d] = (int32_t)mp.slot_part.size();
             t->nempty[d] = (int32_t)mp.empty_rows.size();
             t->max_load[d] = mp.max_load;
-            t->hot_rows[d] = mp.hot_rows;
             if ((st = upload(t, &t->ptr[d], mp.ptr, s)) != SPT_OK) break;
             if ((st = upload(t, &t->psplit_ptr[d], mp.psplit_ptr, s)) != SPT_OK) break;
             if ((st = upload(t, &t->psplit_row[d], mp.psplit_row, s)) != SPT_OK) break;
@@ -715,7 +611,6 @@ spt_status spt_tensor_load_coo(int32_t nmodes, const int64_t* dims, int64_t nnz,
             t->nslots[d] = (int32_t)mp.slot_part.size();
             t->nempty[d] = (int32_t)mp.empty_rows.size();
             t->max_load[d] = mp.max_load;
-            t->hot_rows[d] = mp.hot_rows;
             if ((st = upload(t, &t->ptr[d], mp.ptr, s)) != SPT_OK) break;
             if ((st = upload(t, &t->psplit_ptr[d], mp.psplit_ptr, s)) != SPT_OK) break;
             if ((st = upload(t, &t->psplit_row[d], mp.psplit_row, s)) != SPT_OK) break;

@@ -2,18 +2,21 @@
 // mode count in ec_n2.hip .. ec_n8.hip), the split-row fixup, the BF16 copy
 // of the factors and the remap along a chain of next positions.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "kernels.hpp"
 
 namespace spt {
 
-EcFnPtr pick_ec_n2(int, int, int, int);
-EcFnPtr pick_ec_n3(int, int, int, int);
-EcFnPtr pick_ec_n4(int, int, int, int);
-EcFnPtr pick_ec_n5(int, int, int, int);
-EcFnPtr pick_ec_n6(int, int, int, int);
-EcFnPtr pick_ec_n7(int, int, int, int);
-EcFnPtr pick_ec_n8(int, int, int, int);
+EcFnPtr pick_ec_n2(int, int, int, int, bool);
+EcFnPtr pick_ec_n3(int, int, int, int, bool);
+EcFnPtr pick_ec_n4(int, int, int, int, bool);
+EcFnPtr pick_ec_n5(int, int, int, int, bool);
+EcFnPtr pick_ec_n6(int, int, int, int, bool);
+EcFnPtr pick_ec_n7(int, int, int, int, bool);
+EcFnPtr pick_ec_n8(int, int, int, int, bool);
 
 namespace {
 
@@ -110,67 +113,62 @@ __global__ void remap_kernel(const uint32_t* __restrict__ in, uint32_t* __restri
     }
 }
 
-EcFnPtr pick_ec(int nmodes, int rank, int fdtype, int words, int kind) {
+EcFnPtr pick_ec(int nmodes, int rank, int fdtype, int words, int kind, bool reuse) {
     switch (nmodes) {
-        case 2: return pick_ec_n2(rank, fdtype, words, kind);
-        case 3: return pick_ec_n3(rank, fdtype, words, kind);
-        case 4: return pick_ec_n4(rank, fdtype, words, kind);
-        case 5: return pick_ec_n5(rank, fdtype, words, kind);
-        case 6: return pick_ec_n6(rank, fdtype, words, kind);
-        case 7: return pick_ec_n7(rank, fdtype, words, kind);
-        case 8: return pick_ec_n8(rank, fdtype, words, kind);
+        case 2: return pick_ec_n2(rank, fdtype, words, kind, reuse);
+        case 3: return pick_ec_n3(rank, fdtype, words, kind, reuse);
+        case 4: return pick_ec_n4(rank, fdtype, words, kind, reuse);
+        case 5: return pick_ec_n5(rank, fdtype, words, kind, reuse);
+        case 6: return pick_ec_n6(rank, fdtype, words, kind, reuse);
+        case 7: return pick_ec_n7(rank, fdtype, words, kind, reuse);
+        case 8: return pick_ec_n8(rank, fdtype, words, kind, reuse);
         default: return nullptr;
     }
 }
 
-struct DeviceLimits {
-    int cus = 0;
-    int lds = 0;  // bytes of LDS a workgroup may use
-};
+// Workgroups of f one CU holds at once (0 if the query fails).
+int resident_blocks(EcFnPtr f) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(f), 64, 0) != hipSuccess)
+        return 0;
+    return nb;
+}
 
-// CU count and LDS limit of the current device (queried once per device)
-bool device_limits(DeviceLimits* out) {
-    static DeviceLimits cache[64];
+// The elementwise kernel of a combination: the form that reuses the last
+// gathered row when it keeps the occupancy of the plain form, else the plain
+// form (decided once per combination and device).
+EcFnPtr choose_ec(int nmodes, int rank, int fdtype, int words, int kind) {
+#ifdef SPT_EC_FORM  // build option: 0 = always the plain form, 1 = always the reuse form
+    return pick_ec(nmodes, rank, fdtype, words, kind, SPT_EC_FORM != 0);
+#endif
+    const EcFnPtr plain = pick_ec(nmodes, rank, fdtype, words, kind, false);
+    const EcFnPtr reuse = pick_ec(nmodes, rank, fdtype, words, kind, true);
+    if (!plain || !reuse) return plain;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
-    if (cache[dev].cus == 0) {
-        int cus = 0, lds = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
-        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return false;
-        cache[dev].lds = lds;
-        cache[dev].cus = cus;
-    }
-    *out = cache[dev];
-    return true;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return plain;
+    static std::mutex mu;
+    static std::map<std::pair<int, EcFnPtr>, EcFnPtr> chosen;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = chosen.find({dev, plain});
+    if (it != chosen.end()) return it->second;
+    const int occ_plain = resident_blocks(plain), occ_reuse = resident_blocks(reuse);
+    const EcFnPtr f = occ_reuse > 0 && occ_reuse >= occ_plain ? reuse : plain;
+    chosen[{dev, plain}] = f;
+    return f;
 }
 
 }  // namespace
 
 bool pick_ec_exists(int nmodes, int rank, int fdtype, int words, int kind) {
-    return pick_ec(nmodes, rank, fdtype, words, kind) != nullptr;
-}
-
-int ec_hot_lds_bytes(int nmodes, int rank, int fdtype, int words, int kind) {
-    const EcFnPtr f = pick_ec(nmodes, rank, fdtype, words, kind);
-    DeviceLimits lim;
-    if (!f || !device_limits(&lim)) return -1;
-    hipFuncAttributes attr{};
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(f)) != hipSuccess) return -1;
-    return std::max(0, lim.lds - (int)attr.sharedSizeBytes);
+    return pick_ec(nmodes, rank, fdtype, words, kind, false) != nullptr;
 }
 
 bool launch_ec(int nmodes, int rank, int fdtype, int words, int kind, int kappa, const EcArgs& a,
-               int hot_bytes, hipStream_t s) {
-    const EcFnPtr f = pick_ec(nmodes, rank, fdtype, words, kind);
-    DeviceLimits lim;
-    if (!f || !device_limits(&lim)) return false;
-    if (kappa <= 0) return true;
-    if (hot_bytes > 0 &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            hot_bytes) != hipSuccess)
-        return false;
-    const unsigned grid = (unsigned)std::min<int64_t>(lim.cus, kappa);
-    hipLaunchKernelGGL(f, dim3(grid), dim3(64 * ec_waves(nmodes, rank, fdtype ? 2 : 4)), (size_t)hot_bytes, s, a);
+               hipStream_t s) {
+    if (kappa <= 0) return pick_ec(nmodes, rank, fdtype, words, kind, false) != nullptr;
+    const EcFnPtr f = choose_ec(nmodes, rank, fdtype, words, kind);
+    if (!f) return false;
+    hipLaunchKernelGGL(f, dim3((unsigned)kappa), dim3(64), 0, s, a);
     return true;
 }
 

@@ -1,4 +1,4 @@
-// Elementwise computation (Alg. 2) and dynamic remapping (Alg. 3) for
+// Fused elementwise computation (Alg. 2) and dynamic remapping (Alg. 3) for
 // one output mode, mapped to gfx950 wavefronts (the role of Alg. 4).
 //
 // One workgroup = one wave64 = one partition B_{d,z} of Alg. 1.  A nonzero
@@ -28,7 +28,6 @@
 #ifndef SPT_GATHER_INFLIGHT
 #define SPT_GATHER_INFLIGHT 16
 #endif
-
 namespace spt {
 namespace {
 
@@ -128,371 +127,330 @@ __device__ __forceinline__ void store_vals(float* dst, const float (&v)[V]) {
         *reinterpret_cast<float4*>(dst + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
 }
 
-// Value of `v` in lane `src` of the wave (0 <= src < 64; every lane active).
-__device__ __forceinline__ uint32_t lane_get(uint32_t v, int src) {
-    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
-}
-__device__ __forceinline__ float lane_get(float v, int src) {
-    return __uint_as_float(lane_get(__float_as_uint(v), src));
-}
-
-// Slot of factor row c in a direct-mapped table of h slots (multiplicative
-// hash; the host builds the tag tables with the same function).
-__device__ __forceinline__ uint32_t hot_slot(uint32_t c, uint32_t h) {
-    return __umulhi(c * 0x9E3779B1u, h);
-}
-
-// Words of a decoded record: the N indices, the value's bits, the carry slot.
-template <int N>
-struct Words {
-    uint32_t w[N + 2];
-};
-
-template <int RW, int KIND, int N, int... W>
-__device__ __forceinline__ void decode_words(const Rec<RW>& r, const EcArgs& a, Words<N>& o,
-                                             std::integer_sequence<int, W...>) {
-    ((o.w[W] = decode<W, RW, KIND>(r, a)), ...);
-}
-
-// o.w[idx] for idx < N: an element of a vector value selected at run time
-// (a chain of conditional moves; indexing a register array at run time would
-// put it in scratch memory)
-typedef uint32_t Word8 __attribute__((ext_vector_type(8)));
-template <int N>
-__device__ __forceinline__ uint32_t pick_word(const Words<N>& o, int idx) {
-    Word8 v = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = o.w[i];
-    return v[idx & 7];
-}
-
-template <int N, int R, int RW, int KIND, typename FT, int WPB>
-__global__ __launch_bounds__(64 * WPB) void ec_kernel(const EcArgs a) {
+// REUSE: the last gathered mode's row (mode d-1, the second key of mode d's
+// stream order, so consecutive nonzeros often share it) is fetched once per
+// run of consecutive nonzeros that share it and their output row and kept in
+// registers; every nonzero still multiplies it into its product in the same
+// order, so both forms give the same bits.  Without REUSE every nonzero
+// fetches all its gathered rows.  REUSE costs registers; the launch takes it
+// only where it keeps the occupancy.
+template <int N, int R, int RW, int KIND, typename FT, bool REUSE>
+__global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
     constexpr int V = FT::kPerLoad;
     constexpr int L = R / V;     // lanes per nonzero
     constexpr int G = 64 / L;    // lane groups = nonzeros in flight
     constexpr int NG = N - 1;    // gathered factor rows per nonzero
-    constexpr int RQ = R * FT::kBytes / 16;  // 16-byte words per factor row
     // nonzeros whose gathers are issued together: the largest divisor of L
     // with at most SPT_GATHER_INFLIGHT float4 gathers in flight per lane
     constexpr int BMAX = (SPT_GATHER_INFLIGHT / NG) > 0 ? SPT_GATHER_INFLIGHT / NG : 1;
     constexpr int B = L <= BMAX ? L : (L / 2 <= BMAX ? L / 2 : (L / 4 <= BMAX ? L / 4 : (L / 8 <= BMAX ? L / 8 : 1)));
-    static_assert(R % V == 0 && L >= 1 && 64 % L == 0 && L % B == 0 && RQ == L, "rank");
-    constexpr uint32_t kHot = 0x80000000u;  // marks an LDS slot in place of a row
-    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    static_assert(R % V == 0 && L >= 1 && 64 % L == 0 && L % B == 0, "rank");
+    // staged words per nonzero: indices in mode order, value, carry slot
+    constexpr int SW = N + 2;
+    constexpr int MAXSPLIT = 64;  // split rows of a partition kept in LDS
 
-    // the hot rows of the gathered factors: tags, then rows
-    HIP_DYNAMIC_SHARED(uint4, hot_lds)
+    __shared__ uint32_t stage[SW][64];
+    __shared__ float part[2][G][R];   // [0] head, [1] tail partial of a group
+    __shared__ int32_t prow[2][G];
+    __shared__ int32_t pslot[2][G];
+    __shared__ int32_t gflag[G];      // bit 0 open-left, bit 1 open-right, bit 2 non-empty
+    __shared__ uint32_t brow[G][4];   // rows at the sub-range boundaries
+    __shared__ int32_t srow[MAXSPLIT], sslot[MAXSPLIT];
 
-    const int wv = threadIdx.x / 64;
-    const int lane = threadIdx.x % 64;
+    const int z = blockIdx.x;
+    const int lane = threadIdx.x;
     const int g = lane / L;
     const int li = lane % L;
+    const int64_t s = a.ptr[z];
+    const int64_t n = a.ptr[z + 1] - s;
+    if (n == 0) return;
+    const int sp0 = a.psplit_ptr[z], sp1 = a.psplit_ptr[z + 1];
+    const int nsp = sp1 - sp0;
+    const bool sp_lds = nsp <= MAXSPLIT;
+    if (sp_lds && lane < nsp) {
+        srow[lane] = a.psplit_row[sp0 + lane];
+        sslot[lane] = a.psplit_slot[sp0 + lane];
+    }
     const int mode = a.rot[0];
     constexpr auto seq = std::make_integer_sequence<int, N>{};
 
-    // ---- gathered mode k (1..N-1) keeps hot_h[k] rows in LDS: all rows of
-    // the mode (hot_full: slot = row), or a direct-mapped table whose tag
-    // says which row each slot holds (-1: none)
-    int32_t* const tags = reinterpret_cast<int32_t*>(hot_lds);
-#pragma unroll
-    for (int k = 1; k < N; ++k) {
-        const int h = a.hot_h[k];
-        if (h == 0) continue;
-        if (!a.hot_full[k])
-            for (int i = threadIdx.x; i < h; i += 64 * WPB) tags[a.hot_tag_off[k] + i] = a.hot_tag[k][i];
-        const uint4* src = static_cast<const uint4*>(a.fac[k]);
-        for (int i = threadIdx.x; i < h * RQ; i += 64 * WPB) {
-            const int sl = i / RQ;
-            const int row = a.hot_full[k] ? sl : a.hot_tag[k][sl];
-            if (row >= 0) hot_lds[a.hot_row_off[k] + i] = src[(int64_t)row * RQ + i % RQ];
+    const int64_t q = n / G, rm = n % G;
+    const int64_t gs = s + g * q + (g < rm ? g : rm);
+    const int gn = (int)(q + (g < rm ? 1 : 0));
+    const int64_t ge = gs + gn;
+
+    // output rows around the group's sub-range: before, first, last, after
+    for (int j = li; j < 4; j += L) {
+        const int64_t p = j == 0 ? gs - 1 : j == 1 ? gs : j == 2 ? ge - 1 : ge;
+        uint32_t row = 0xFFFFFFFFu;
+        if (gn > 0 && p >= s && p < s + n) {
+            Rec<RW> r;
+            load_rec<RW>(a.rec_in, p, r);
+            decode_all<RW, KIND>(r, a, stage, lane, seq);
+            row = stage[mode][lane];
         }
+        brow[g][j] = row;
+    }
+    __syncthreads();
+    const bool open_left = gn > 0 && brow[g][0] != 0xFFFFFFFFu && brow[g][0] == brow[g][1];
+    const bool open_right = gn > 0 && brow[g][3] != 0xFFFFFFFFu && brow[g][3] == brow[g][2];
+    if (li == 0) {
+        gflag[g] = (open_left ? 1 : 0) | (open_right ? 2 : 0) | (gn > 0 ? 4 : 0);
+        prow[0][g] = -1;
+        prow[1][g] = -1;
     }
     __syncthreads();
 
-    // ---- the wave's partitions: z = block + grid * (wave + WPB * j)
-    for (int64_t z = blockIdx.x + (int64_t)gridDim.x * wv; z < a.kappa; z += (int64_t)gridDim.x * WPB) {
-        const int64_t s = a.ptr[z];
-        const int64_t n = a.ptr[z + 1] - s;
-        if (n == 0) continue;
-        // rows of this partition split across partitions, one per lane
-        const int sp0 = a.psplit_ptr[z], sp1 = a.psplit_ptr[z + 1];
-        const int nsp = sp1 - sp0;
-        const bool sp_reg = nsp <= 64;
-        int32_t my_srow = -1, my_sslot = -1;
-        if (sp_reg && lane < nsp) {
-            my_srow = a.psplit_row[sp0 + lane];
-            my_sslot = a.psplit_slot[sp0 + lane];
+    // acc: the output row's sum so far; ylast (REUSE): the last gathered
+    // mode's row of the current run of equal (output row, last gathered row)
+    float acc[V], ylast[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        acc[v] = 0.0f;
+        ylast[v] = 0.0f;
+    }
+    int cur_row = -1, cur_slot = -1;
+    uint32_t cur_lrow = 0xFFFFFFFFu;  // last gathered mode's row of the current run
+    bool first_seg = true;
+    const int steps = (int)(q + (rm > 0 ? 1 : 0));
+    const bool remap = a.rec_out != nullptr;
+    const bool remap_inline = remap;
+
+    // carry slot of a row of this partition (-1: not a split row)
+    auto slot_of = [&](int row) {
+        int slot = -1;
+        if (sp_lds) {
+            for (int j = 0; j < nsp; ++j)
+                if (srow[j] == row) slot = sslot[j];
+        } else {
+            slot = split_slot(a, sp0, sp1, row);
         }
-        // carry slot of a row of this partition (-1: not a split row)
-        auto slot_of = [&](uint32_t row) {
-            int slot = -1;
-            if (sp_reg) {
-                for (int j = 0; j < nsp; ++j) {
-                    const uint32_t r = (uint32_t)__builtin_amdgcn_readlane(my_srow, j);
-                    const int sl = __builtin_amdgcn_readlane(my_sslot, j);
-                    if (r == row) slot = sl;
-                }
-            } else {
-                slot = split_slot(a, sp0, sp1, (int)row);
+        return slot;
+    };
+
+    // One step: commit the record fetched for this step (remap store,
+    // decode), prefetch the next step's record into the other buffer after
+    // the first gathers, then run the lane groups over their L nonzeros of
+    // this step.  Two record buffers alternate, so a prefetch never
+    // overwrites the registers of a remap store still in flight.
+    Rec<RW> ra, rb;
+    int32_t na = 0, nb = 0;
+    if (li < gn) {
+        load_rec<RW>(a.rec_in, gs + li, ra);
+        if (remap_inline) na = a.nxt[gs + li];
+    }
+    auto step = [&](int step0, Rec<RW>& cur, int32_t& ncur, Rec<RW>& nxt_rec, int32_t& nnext) {
+        if (step0 + li < gn) {
+            if (remap_inline) store_rec<RW>(a.rec_out, ncur, cur);
+            decode_all<RW, KIND>(cur, a, stage, lane, seq);
+            stage[N][lane] = rword<RW - 1, RW>(cur);
+            stage[N + 1][lane] = (uint32_t)slot_of((int)stage[mode][lane]);
+        }
+        __syncthreads();
+        const int cnt = gn - step0;
+        #pragma unroll
+        for (int kb = 0; kb < L; kb += B) {
+            uint4 y[B][NG];
+            // the last gathered mode's row is fetched only where a run of
+            // equal (output row, last gathered row) starts: the same test the
+            // accumulation below makes, against the previous nonzero
+            bool fresh[B];
+            #pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int slot = g * L + kb + b;
+                const uint32_t prow_b = b == 0 ? (uint32_t)cur_row : stage[mode][slot - 1];
+                const uint32_t plrow_b = b == 0 ? cur_lrow : stage[a.rot[NG]][slot - 1];
+                fresh[b] = !REUSE || stage[mode][slot] != prow_b || stage[a.rot[NG]][slot] != plrow_b;
             }
-            return slot;
-        };
-
-        const int64_t q = n / G, rm = n % G;
-        const int64_t gs = s + g * q + (g < rm ? g : rm);
-        const int gn = (int)(q + (g < rm ? 1 : 0));
-        const int64_t ge = gs + gn;
-
-        // output rows around the group's sub-range: before, first, last, after
-        uint32_t brow[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t p = j == 0 ? gs - 1 : j == 1 ? gs : j == 2 ? ge - 1 : ge;
-            brow[j] = kNone;
-            if (gn > 0 && p >= s && p < s + n) {
-                Rec<RW> r;
-                load_rec<RW>(a.rec_in, p, r);
-                Words<N> wd;
-                decode_words<RW, KIND>(r, a, wd, seq);
-                brow[j] = pick_word(wd, mode);
-            }
-        }
-        const bool open_left = gn > 0 && brow[0] != kNone && brow[0] == brow[1];
-        const bool open_right = gn > 0 && brow[3] != kNone && brow[3] == brow[2];
-
-        float acc[V], head[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            acc[v] = 0.0f;
-            head[v] = 0.0f;
-        }
-        int cur_row = -1, cur_slot = -1, head_row = -1;
-        bool first_seg = true;
-        const int steps = (int)(q + (rm > 0 ? 1 : 0));
-        const bool remap_inline = a.rec_out != nullptr;
-
-        // One step: commit the record fetched for this step (remap store,
-        // decode), prefetch the next step's record into the other buffer
-        // after the first gathers, then run the lane groups over their L
-        // nonzeros of this step.  Two record buffers alternate, so a prefetch
-        // never overwrites the registers of a remap store still in flight.
-        Rec<RW> ra, rb;
-        int32_t na = 0, nb = 0;
-        if (li < gn) {
-            load_rec<RW>(a.rec_in, gs + li, ra);
-            if (remap_inline) na = a.nxt[gs + li];
-        }
-        // the lane's record: indices in rotated mode order (w[k] = index of
-        // mode (d + k) mod N), then the value's bits and the carry slot
-        Words<N> mine;
-#pragma unroll
-        for (int k = 0; k < N + 2; ++k) mine.w[k] = 0u;
-        auto step = [&](int step0, Rec<RW>& cur, int32_t& ncur, Rec<RW>& nxt_rec, int32_t& nnext) {
-            if (step0 + li < gn) {
-                if (remap_inline) store_rec<RW>(a.rec_out, ncur, cur);
-                Words<N> dec;
-                decode_words<RW, KIND>(cur, a, dec, seq);
-#pragma unroll
-                for (int k = 0; k < N; ++k) mine.w[k] = pick_word(dec, a.rot[k]);
-                mine.w[N] = rword<RW - 1, RW>(cur);
-            }
-            // every lane (the lookup reads other lanes); lanes past the
-            // group's range look up a stale row and never use it
-            mine.w[N + 1] = (uint32_t)slot_of(mine.w[0]);
-            const int cnt = gn - step0;
-#pragma unroll
-            for (int kb = 0; kb < L; kb += B) {
-                // each gathered row: its LDS slot (with kHot) when it is hot,
-                // else its row in memory
-                uint32_t c[B][NG];
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const int src = g * L + kb + b;
-#pragma unroll
-                    for (int k = 0; k < NG; ++k) {
-                        const uint32_t row = lane_get(mine.w[k + 1], src);
-                        const int h = a.hot_h[k + 1];
-                        uint32_t cc = row;
-                        if (h > 0) {
-                            if (a.hot_full[k + 1]) {
-                                cc = kHot | row;
-                            } else {
-                                const uint32_t sl = hot_slot(row, (uint32_t)h);
-                                if (tags[a.hot_tag_off[k + 1] + sl] == (int32_t)row) cc = kHot | sl;
-                            }
-                        }
-                        c[b][k] = cc;
+            #pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int slot = g * L + kb + b;
+                const bool live = kb + b < cnt;
+                #pragma unroll
+                for (int k = 0; k < NG; ++k) {
+                    if (live && (k < NG - 1 || fresh[b])) {
+                        y[b][k] = *reinterpret_cast<const uint4*>(
+                            static_cast<const char*>(a.fac[k + 1]) +
+                            ((int64_t)stage[a.rot[k + 1]][slot] * R + li * V) * FT::kBytes);
                     }
                 }
-                uint4 y[B][NG];
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const bool live = kb + b < cnt;
-#pragma unroll
-                    for (int k = 0; k < NG; ++k) {
-                        if (live) {
-                            if (c[b][k] & kHot)
-                                y[b][k] = hot_lds[a.hot_row_off[k + 1] + (int)(c[b][k] & ~kHot) * RQ + li];
-                            else
-                                y[b][k] = static_cast<const uint4*>(a.fac[k + 1])[(int64_t)c[b][k] * RQ + li];
-                        }
+            }
+            if (kb == 0 && step0 + L + li < gn) {
+                load_rec<RW>(a.rec_in, gs + step0 + L + li, nxt_rec);
+                if (remap_inline) nnext = a.nxt[gs + step0 + L + li];
+            }
+            #pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (kb + b < cnt) {
+                    const int slot = g * L + kb + b;
+                    const int row = (int)stage[mode][slot];
+                    if (REUSE && fresh[b]) {
+                        widen<FT>(y[b][NG - 1], ylast);
+                        cur_lrow = stage[a.rot[NG]][slot];
                     }
-                }
-                if (kb == 0 && step0 + L + li < gn) {
-                    load_rec<RW>(a.rec_in, gs + step0 + L + li, nxt_rec);
-                    if (remap_inline) nnext = a.nxt[gs + step0 + L + li];
-                }
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const int src = g * L + kb + b;
-                    const int row = (int)lane_get(mine.w[0], src);
-                    const float val = __uint_as_float(lane_get(mine.w[N], src));
-                    const int rslot = (int)lane_get(mine.w[N + 1], src);
-                    if (kb + b < cnt) {
-                        if (row != cur_row) {
-                            if (cur_row >= 0) {
-                                if (first_seg && open_left) {
-#pragma unroll
-                                    for (int v = 0; v < V; ++v) head[v] = acc[v];
-                                    head_row = cur_row;
-                                } else {
-                                    store_vals<V>(row_dst<R>(a, cur_row, cur_slot) + li * V, acc);
+                    if (row != cur_row) {
+                        if (cur_row >= 0) {
+                            if (first_seg && open_left) {
+                                store_vals<V>(&part[0][g][li * V], acc);
+                                if (li == 0) {
+                                    prow[0][g] = cur_row;
+                                    pslot[0][g] = cur_slot;
                                 }
-                                first_seg = false;
+                            } else {
+                                store_vals<V>(row_dst<R>(a, cur_row, cur_slot) + li * V, acc);
                             }
-                            cur_row = row;
-                            cur_slot = rslot;
-#pragma unroll
-                            for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+                            first_seg = false;
                         }
+                        cur_row = row;
+                        cur_slot = (int)stage[N + 1][slot];
+                        #pragma unroll
+                        for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+                    }
+                    const float val = __uint_as_float(stage[N][slot]);
+                    if constexpr (REUSE) {
+                        // the product of the gathered rows in mode order, the
+                        // last one from the registers of its run
+                        float prod[V];
+                        if constexpr (NG == 1) {
+                            #pragma unroll
+                            for (int v = 0; v < V; ++v) prod[v] = ylast[v];
+                        } else {
+                            widen<FT>(y[b][0], prod);
+                            #pragma unroll
+                            for (int k = 1; k < NG - 1; ++k) {
+                                float f[V];
+                                widen<FT>(y[b][k], f);
+                                #pragma unroll
+                                for (int v = 0; v < V; ++v) prod[v] *= f[v];
+                            }
+                            #pragma unroll
+                            for (int v = 0; v < V; ++v) prod[v] *= ylast[v];
+                        }
+                        #pragma unroll
+                        for (int v = 0; v < V; ++v) acc[v] = fmaf(prod[v], val, acc[v]);
+                    } else {
                         float prod[V];
                         widen<FT>(y[b][0], prod);
-#pragma unroll
+                        #pragma unroll
                         for (int k = 1; k < NG; ++k) {
                             float f[V];
                             widen<FT>(y[b][k], f);
-#pragma unroll
+                            #pragma unroll
                             for (int v = 0; v < V; ++v) prod[v] *= f[v];
                         }
-#pragma unroll
+                        #pragma unroll
                         for (int v = 0; v < V; ++v) acc[v] = fmaf(prod[v], val, acc[v]);
                     }
                 }
             }
-        };
-        for (int t = 0; t < steps; t += 2 * L) {
-            step(t, ra, na, rb, nb);
-            if (t + L < steps) step(t + L, rb, nb, ra, na);
         }
+        __syncthreads();
+    
+    };
+    for (int t = 0; t < steps; t += 2 * L) {
+        step(t, ra, na, rb, nb);
+        if (t + L < steps) step(t + L, rb, nb, ra, na);
+    }
 
-        // the group's last segment: kept (the tail) when the next group or
-        // the head chain continues it, else stored
-        int tail_row = -1, tail_slot = -1;
-        if (cur_row >= 0) {
-            if (open_right || (first_seg && open_left)) {
-                tail_row = cur_row;
-                tail_slot = cur_slot;
-            } else {
-                store_vals<V>(row_dst<R>(a, cur_row, cur_slot) + li * V, acc);
+    // the group's last segment
+    if (cur_row >= 0) {
+        if (open_right || (first_seg && open_left)) {
+            store_vals<V>(&part[1][g][li * V], acc);
+            if (li == 0) {
+                prow[1][g] = cur_row;
+                pslot[1][g] = cur_slot;
             }
+        } else {
+            store_vals<V>(row_dst<R>(a, cur_row, cur_slot) + li * V, acc);
         }
+    }
+    __syncthreads();
 
-        // chain combine across groups in group order (every group computes
-        // it, group 0 stores): a row that crosses sub-range boundaries is the
-        // tail of one group, whole groups, and the head of another
-        const int flags = (open_left ? 1 : 0) | (open_right ? 2 : 0) | (gn > 0 ? 4 : 0);
-        float csum[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) csum[v] = 0.0f;
+    // chain combine across groups, lanes over ranks, in group order
+    for (int r0 = 0; r0 < R; r0 += 64) {
+        const int rk = r0 + lane;
+        const bool active = rk < R;
+        float csum = 0.0f;
         int crow = -1, cslot = -1;
-        auto flush = [&]() {
-            if (crow >= 0 && g == 0) store_vals<V>(row_dst<R>(a, crow, cslot) + li * V, csum);
-        };
         for (int h = 0; h < G; ++h) {
-            const int f = (int)lane_get((uint32_t)flags, h * L);
-            const int hr = (int)lane_get((uint32_t)head_row, h * L);
-            const int tr = (int)lane_get((uint32_t)tail_row, h * L);
-            const int ts = (int)lane_get((uint32_t)tail_slot, h * L);
-            float hv[V], tv[V];
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                hv[v] = lane_get(head[v], h * L + li);
-                tv[v] = lane_get(acc[v], h * L + li);
-            }
+            const int f = gflag[h];
             if (!(f & 4)) continue;
-            if (f & 1) {
-                if (hr >= 0) {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) csum[v] += hv[v];
-                    flush();
+            const bool ol = f & 1, orr = f & 2;
+            auto flush = [&](int row, int slot, float x) {
+                if (row < 0) return;
+                if (active) row_dst<R>(a, row, slot)[rk] = x;
+            };
+            if (ol) {
+                if (prow[0][h] >= 0) {
+                    csum += active ? part[0][h][rk] : 0.0f;
+                    flush(crow, cslot, csum);
                     crow = -1;
-#pragma unroll
-                    for (int v = 0; v < V; ++v) csum[v] = 0.0f;
-                    if (tr >= 0) {
-                        crow = tr;
-                        cslot = ts;
-#pragma unroll
-                        for (int v = 0; v < V; ++v) csum[v] = tv[v];
+                    csum = 0.0f;
+                    if (prow[1][h] >= 0) {
+                        crow = prow[1][h];
+                        cslot = pslot[1][h];
+                        csum = active ? part[1][h][rk] : 0.0f;
                     }
                 } else {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) csum[v] += tv[v];
-                    if (!(f & 2)) {
-                        flush();
+                    csum += active ? part[1][h][rk] : 0.0f;
+                    if (!orr) {
+                        flush(crow, cslot, csum);
                         crow = -1;
-#pragma unroll
-                        for (int v = 0; v < V; ++v) csum[v] = 0.0f;
+                        csum = 0.0f;
                     }
                 }
-            } else if (tr >= 0) {
-                crow = tr;
-                cslot = ts;
-#pragma unroll
-                for (int v = 0; v < V; ++v) csum[v] = tv[v];
+            } else if (prow[1][h] >= 0) {
+                crow = prow[1][h];
+                cslot = pslot[1][h];
+                csum = active ? part[1][h][rk] : 0.0f;
             }
         }
-    }  // partitions
+    }
 }
 
 using EcFn = EcFnPtr;
 
-template <int N, int RW, int KIND>
+template <int N, int RW, int KIND, bool REUSE>
 EcFn pick_rank(int rank, int fdtype) {
     if (fdtype == 0) {
         switch (rank) {
-            case 8: return ec_kernel<N, 8, RW, KIND, FacF32, ec_waves(N, 8, 4)>;
-            case 16: return ec_kernel<N, 16, RW, KIND, FacF32, ec_waves(N, 16, 4)>;
-            case 32: return ec_kernel<N, 32, RW, KIND, FacF32, ec_waves(N, 32, 4)>;
-            case 64: return ec_kernel<N, 64, RW, KIND, FacF32, ec_waves(N, 64, 4)>;
-            case 128: return ec_kernel<N, 128, RW, KIND, FacF32, ec_waves(N, 128, 4)>;
+            case 8: return ec_kernel<N, 8, RW, KIND, FacF32, REUSE>;
+            case 16: return ec_kernel<N, 16, RW, KIND, FacF32, REUSE>;
+            case 32: return ec_kernel<N, 32, RW, KIND, FacF32, REUSE>;
+            case 64: return ec_kernel<N, 64, RW, KIND, FacF32, REUSE>;
+            case 128: return ec_kernel<N, 128, RW, KIND, FacF32, REUSE>;
             default: return nullptr;
         }
     }
     switch (rank) {
-        case 8: return ec_kernel<N, 8, RW, KIND, FacBF16, ec_waves(N, 8, 2)>;
-        case 16: return ec_kernel<N, 16, RW, KIND, FacBF16, ec_waves(N, 16, 2)>;
-        case 32: return ec_kernel<N, 32, RW, KIND, FacBF16, ec_waves(N, 32, 2)>;
-        case 64: return ec_kernel<N, 64, RW, KIND, FacBF16, ec_waves(N, 64, 2)>;
-        case 128: return ec_kernel<N, 128, RW, KIND, FacBF16, ec_waves(N, 128, 2)>;
+        case 8: return ec_kernel<N, 8, RW, KIND, FacBF16, REUSE>;
+        case 16: return ec_kernel<N, 16, RW, KIND, FacBF16, REUSE>;
+        case 32: return ec_kernel<N, 32, RW, KIND, FacBF16, REUSE>;
+        case 64: return ec_kernel<N, 64, RW, KIND, FacBF16, REUSE>;
+        case 128: return ec_kernel<N, 128, RW, KIND, FacBF16, REUSE>;
         default: return nullptr;
     }
 }
 
+template <int N, int RW, int KIND>
+EcFn pick_rank(int rank, int fdtype, bool reuse) {
+    return reuse ? pick_rank<N, RW, KIND, true>(rank, fdtype) : pick_rank<N, RW, KIND, false>(rank, fdtype);
+}
+
 // (record words, layout kind) pairs the planner can choose for N modes
 template <int N>
-EcFn pick_layout(int rank, int fdtype, int words, int kind) {
+EcFn pick_layout(int rank, int fdtype, int words, int kind, bool reuse) {
     if constexpr (N <= 3) {
-        if (words == 4 && kind == kWord32) return pick_rank<N, 4, kWord32>(rank, fdtype);
+        if (words == 4 && kind == kWord32) return pick_rank<N, 4, kWord32>(rank, fdtype, reuse);
     } else if constexpr (N <= 6) {
-        if (words == 4 && kind == kHalf16) return pick_rank<N, 4, kHalf16>(rank, fdtype);
-        if (words == 4 && kind == kPacked) return pick_rank<N, 4, kPacked>(rank, fdtype);
-        if (words == 8 && kind == kWord32) return pick_rank<N, 8, kWord32>(rank, fdtype);
+        if (words == 4 && kind == kHalf16) return pick_rank<N, 4, kHalf16>(rank, fdtype, reuse);
+        if (words == 4 && kind == kPacked) return pick_rank<N, 4, kPacked>(rank, fdtype, reuse);
+        if (words == 8 && kind == kWord32) return pick_rank<N, 8, kWord32>(rank, fdtype, reuse);
     } else if constexpr (N == 7) {
-        if (words == 8 && kind == kWord32) return pick_rank<N, 8, kWord32>(rank, fdtype);
+        if (words == 8 && kind == kWord32) return pick_rank<N, 8, kWord32>(rank, fdtype, reuse);
     } else {
-        if (words == 8 && kind == kHalf16) return pick_rank<N, 8, kHalf16>(rank, fdtype);
-        if (words == 12 && kind == kWord32) return pick_rank<N, 12, kWord32>(rank, fdtype);
+        if (words == 8 && kind == kHalf16) return pick_rank<N, 8, kHalf16>(rank, fdtype, reuse);
+        if (words == 12 && kind == kWord32) return pick_rank<N, 12, kWord32>(rank, fdtype, reuse);
     }
     return nullptr;
 }

@@ -4,8 +4,8 @@
 
 namespace spt {
 
-EcFnPtr pick_ec_n5(int rank, int fdtype, int words, int kind) {
-    return pick_layout<5>(rank, fdtype, words, kind);
+EcFnPtr pick_ec_n5(int rank, int fdtype, int words, int kind, bool reuse) {
+    return pick_layout<5>(rank, fdtype, words, kind, reuse);
 }
 
 }  // namespace spt

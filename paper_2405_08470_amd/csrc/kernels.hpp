@@ -26,34 +26,7 @@ struct EcArgs {
     int32_t rot[8];            // rot[k] = (d + k) mod N
     int32_t foff[8];           // bit offset of each mode's index (packed layout)
     uint32_t fmask[8];         // width mask of each mode's index (packed layout)
-    int32_t kappa;             // partitions of mode d
-    // hot rows of gathered mode k (rotated, k >= 1) kept in LDS: hot_h[k]
-    // slots (0: none); hot_full[k] = every row of the mode, slot = row;
-    // otherwise slot hot_slot(row, hot_h[k]) holds row hot_tag[k][slot] (-1:
-    // empty)
-    int32_t hot_h[8];
-    int32_t hot_full[8];
-    const int32_t* hot_tag[8];
-    int32_t hot_tag_off[8];    // first tag of mode k in LDS (int32 units)
-    int32_t hot_row_off[8];    // first row of mode k in LDS (16-byte units)
 };
-
-// Waves per workgroup of the elementwise kernel (one workgroup per CU, all
-// of the CU's LDS for hot factor rows): SPT_EC_WAVES when a nonzero's gathered
-// rows are at most SPT_EC_WIDE_BYTES bytes per lane group (the kernel's
-// registers then allow that many waves), else SPT_EC_WAVES_WIDE.
-#ifndef SPT_EC_WAVES
-#define SPT_EC_WAVES 8
-#endif
-#ifndef SPT_EC_WAVES_WIDE
-#define SPT_EC_WAVES_WIDE 8
-#endif
-#ifndef SPT_EC_WIDE_BYTES
-#define SPT_EC_WIDE_BYTES 768
-#endif
-constexpr int ec_waves(int nmodes, int rank, int fbytes) {
-    return (nmodes - 1) * rank * fbytes <= SPT_EC_WIDE_BYTES ? SPT_EC_WAVES : SPT_EC_WAVES_WIDE;
-}
 
 // Forward pass of the gradient fit (grad_kernel.hip).
 struct ForwardArgs {
@@ -79,17 +52,12 @@ struct FixupArgs {
 using EcFnPtr = void (*)(EcArgs);
 
 // fdtype 0: FP32 factors, 1: BF16 factors.  Returns false if the combination
-// (nmodes, rank, factor type, record words, layout kind) has no kernel or the
-// launch failed.  One workgroup of W = ec_waves(...) waves per CU (at most kappa);
-// each wave takes partitions block + grid * (wave + W j).  hot_bytes: the dynamic LDS
-// of the hot-row tables (at most ec_hot_lds_bytes(...)).
+// (nmodes, rank, factor type, record words, layout kind) has no kernel.  One
+// single-wave workgroup per partition (kappa of them).
 bool launch_ec(int nmodes, int rank, int fdtype, int words, int kind, int kappa, const EcArgs& a,
-               int hot_bytes, hipStream_t s);
+               hipStream_t s);
 // true if the combination has an elementwise kernel
 bool pick_ec_exists(int nmodes, int rank, int fdtype, int words, int kind);
-// LDS bytes the elementwise kernel of this combination leaves for hot rows on
-// the current device (-1: no such kernel, or a device query failed).
-int ec_hot_lds_bytes(int nmodes, int rank, int fdtype, int words, int kind);
 int forward_blocks(int64_t nnz);
 bool launch_forward(int nmodes, int rank, int words, int kind, const ForwardArgs& a,
                     hipStream_t s);

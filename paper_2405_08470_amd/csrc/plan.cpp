@@ -195,16 +195,6 @@ void partition_rows(int64_t I, const int64_t* deg, int32_t kappa, int64_t cap, M
     mp.empty_rows.clear();
     for (int64_t i = 0; i < I; ++i)
         if (deg[i] == 0) mp.empty_rows.push_back((int32_t)i);
-
-    // the hottest rows (degree >= 2), hottest first, ties to the lower row
-    std::vector<int32_t> cand;
-    for (int64_t i = 0; i < I; ++i)
-        if (deg[i] >= 2) cand.push_back((int32_t)i);
-    auto hotter = [&](int32_t a, int32_t b) { return deg[a] != deg[b] ? deg[a] > deg[b] : a < b; };
-    const size_t keep = std::min<size_t>(cand.size(), (size_t)kHotRows);
-    std::partial_sort(cand.begin(), cand.begin() + keep, cand.end(), hotter);
-    cand.resize(keep);
-    mp.hot_rows = std::move(cand);
 }
 
 int64_t piece_of_rank(int64_t deg, int64_t k, int64_t rank) {

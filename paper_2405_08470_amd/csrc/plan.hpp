@@ -43,14 +43,8 @@ struct ModePlan {
     std::vector<int32_t> psplit_row;  // [nslots]
     std::vector<int32_t> psplit_slot; // [nslots]
     std::vector<int32_t> empty_rows;  // rows with no nonzero
-    // rows of degree >= 2 by decreasing degree, then increasing row, at most
-    // kHotRows of them: the rows whose factor rows the elementwise kernel
-    // keeps in LDS when this mode is gathered
-    std::vector<int32_t> hot_rows;
     int64_t max_load = 0;
 };
-
-constexpr int kHotRows = 16384;
 
 struct Plan {
     int nmodes = 0;

@@ -143,5 +143,6 @@ const char* hipGetErrorString(hipError_t e);
 hipError_t hipGetDevice(int* d);
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int dev);
 hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void* f);
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void* f, int block, size_t lds);
 hipError_t hipFuncSetAttribute(const void* f, hipFuncAttribute a, int v);
 hipError_t hipGetSymbolAddress(void** p, const void* sym);

@@ -324,6 +324,12 @@ hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void*) {
     a->maxThreadsPerBlock = 1024;
     return hipSuccess;
 }
+// every kernel reports the same occupancy, so the library takes the forms
+// it prefers at equal occupancy (builds with SPT_EC_FORM force one)
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void*, int, size_t) {
+    *n = 16;
+    return hipSuccess;
+}
 hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int v) {
     return v <= 160 * 1024 ? hipSuccess : hipErrorInvalidValue;
 }

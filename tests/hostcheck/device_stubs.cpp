@@ -18,11 +18,10 @@ namespace {
 }  // namespace
 
 namespace spt {
-bool launch_ec(int, int, int, int, int, int, const EcArgs&, int, hipStream_t) { reached("launch_ec"); }
+bool launch_ec(int, int, int, int, int, int, const EcArgs&, hipStream_t) { reached("launch_ec"); }
 bool pick_ec_exists(int nmodes, int rank, int, int, int) {
     return nmodes >= 2 && nmodes <= 8 && (rank == 8 || rank == 16 || rank == 32 || rank == 64 || rank == 128);
 }
-int ec_hot_lds_bytes(int, int, int, int, int) { reached("ec_hot_lds_bytes"); }
 int forward_blocks(int64_t) { reached("forward_blocks"); }
 bool launch_forward(int, int, int, int, const ForwardArgs&, hipStream_t) { reached("launch_forward"); }
 void launch_to_bf16(const float*, uint16_t*, int64_t, hipStream_t) { reached("launch_to_bf16"); }
