@@ -250,28 +250,40 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
         const int cnt = gn - step0;
         #pragma unroll
         for (int kb = 0; kb < L; kb += B) {
-            uint4 y[B][NG];
+            // the batch's rows first (one LDS wait for all of them), then its
+            // gathers back to back; a nonzero past the group's range gathers
+            // row 0 (always a valid row) instead of branching around the load
+            uint32_t orow[B], rix[B][NG];
+            #pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int slot = g * L + kb + b;
+                orow[b] = stage[mode][slot];
+                #pragma unroll
+                for (int k = 0; k < NG; ++k) rix[b][k] = stage[a.rot[k + 1]][slot];
+            }
             // the last gathered mode's row is fetched only where a run of
             // equal (output row, last gathered row) starts: the same test the
             // accumulation below makes, against the previous nonzero
             bool fresh[B];
             #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const int slot = g * L + kb + b;
-                const uint32_t prow_b = b == 0 ? (uint32_t)cur_row : stage[mode][slot - 1];
-                const uint32_t plrow_b = b == 0 ? cur_lrow : stage[a.rot[NG]][slot - 1];
-                fresh[b] = !REUSE || stage[mode][slot] != prow_b || stage[a.rot[NG]][slot] != plrow_b;
+                const uint32_t po = b == 0 ? (uint32_t)cur_row : orow[b - 1];
+                const uint32_t pl = b == 0 ? cur_lrow : rix[b - 1][NG - 1];
+                fresh[b] = !REUSE || orow[b] != po || rix[b][NG - 1] != pl;
             }
+            uint4 y[B][NG];
             #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const int slot = g * L + kb + b;
                 const bool live = kb + b < cnt;
                 #pragma unroll
                 for (int k = 0; k < NG; ++k) {
-                    if (live && (k < NG - 1 || fresh[b])) {
-                        y[b][k] = *reinterpret_cast<const uint4*>(
-                            static_cast<const char*>(a.fac[k + 1]) +
-                            ((int64_t)stage[a.rot[k + 1]][slot] * R + li * V) * FT::kBytes);
+                    const uint4* src = reinterpret_cast<const uint4*>(
+                        static_cast<const char*>(a.fac[k + 1]) +
+                        ((int64_t)(live ? rix[b][k] : 0u) * R + li * V) * FT::kBytes);
+                    if (!REUSE || k < NG - 1) {
+                        y[b][k] = *src;
+                    } else if (live && fresh[b]) {
+                        y[b][k] = *src;
                     }
                 }
             }
@@ -283,10 +295,10 @@ __global__ __launch_bounds__(64) void ec_kernel(const EcArgs a) {
             for (int b = 0; b < B; ++b) {
                 if (kb + b < cnt) {
                     const int slot = g * L + kb + b;
-                    const int row = (int)stage[mode][slot];
+                    const int row = (int)orow[b];
                     if (REUSE && fresh[b]) {
                         widen<FT>(y[b][NG - 1], ylast);
-                        cur_lrow = stage[a.rot[NG]][slot];
+                        cur_lrow = rix[b][NG - 1];
                     }
                     if (row != cur_row) {
                         if (cur_row >= 0) {
