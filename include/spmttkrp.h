@@ -65,11 +65,12 @@ typedef struct spt_opts {
     int32_t dr;         /* how a remapping MTTKRP moves the stream to the next
                            mode's order (Alg. 3), copies == 0 only:
                            0 = a second pass after the elementwise kernel
-                           that writes each chunk of 65536 consecutive
-                           records (16-byte records; 32768 / 16384 for 32 /
-                           48 bytes; spt_info.remap_chunk) in destination
-                           order; the load builds its tables, 6 bytes per
-                           nonzero and mode.  1 = fused: the elementwise kernel stores
+                           that writes each chunk of 2 MB of consecutive
+                           records (131072 16-byte records; fewer when the
+                           tables cannot address that many: see
+                           spt_info.remap_chunk) in destination order; the
+                           load builds its tables, 6 bytes per nonzero and
+                           mode.  1 = fused: the elementwise kernel stores
                            every record at its next position.  The next
                            stream is identical either way                   */
     int32_t layout;     /* record layout of the stream (Sec. 3.5): 0 = chosen

@@ -440,10 +440,8 @@ spt_status build_stage_tables(spt_tensor_s* t, hipStream_t s) {
     uint16_t* tmp_off = nullptr;
     spt_status st = SPT_OK;
     const int64_t bytes_before = t->device_bytes;
-    if (spt::stage_tables_need_temp(t->lay.words)) {
-        st = dalloc(t, &tmp_dst, (size_t)t->nnz, &temps);
-        if (st == SPT_OK) st = dalloc(t, &tmp_off, (size_t)t->nnz, &temps);
-    }
+    st = dalloc(t, &tmp_dst, (size_t)t->nnz, &temps);
+    if (st == SPT_OK) st = dalloc(t, &tmp_off, (size_t)t->nnz, &temps);
     const int64_t temp_bytes = t->device_bytes - bytes_before;
     auto free_temps = [&]() {
         for (void* p : temps) (void)hipFree(p);
@@ -725,7 +723,7 @@ spt_status spt_tensor_info(spt_tensor_t t, spt_info* info) {
     info->norm_sq = t->norm_sq;
     info->prep_seconds = t->prep_seconds;
     info->device_bytes = t->device_bytes;
-    info->remap_chunk = t->ddst[0] ? spt::stage_chunk(t->lay.words) : 0;
+    info->remap_chunk = t->ddst[0] ? spt::stage_chunk(t->lay.words, t->nnz) : 0;
     return SPT_OK;
 }
 

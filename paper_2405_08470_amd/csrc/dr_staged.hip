@@ -3,8 +3,8 @@
 //
 // The fused form stores each record at its next-mode position while the
 // elementwise computation runs (one 16-byte store to a random address per
-// nonzero).  Here the stream is cut into chunks of C consecutive records (1 MB
-// of records: 65536 16-byte records), and the records of each chunk are
+// nonzero).  Here the stream is cut into chunks of C consecutive records (2 MB
+// of records: 131072 16-byte records), and the records of each chunk are
 // written in the order of their destinations: consecutive threads take
 // consecutive table slots, so records of one chunk that land next to each
 // other in the next mode's stream go out in the same store instruction and
@@ -16,8 +16,11 @@
 // The next mode's stream is the same as the fused form's, bit for bit.
 //
 // Tables (built once at load, per mode d, from the next positions nxt_d):
-//   ddst[c*C + j] = j-th smallest destination among the records of chunk c
-//   doff[c*C + j] = offset inside chunk c of the record that goes there
+//   ddst[c*C + j] = j-th smallest destination among the records of chunk c,
+//                   in its low dbits bits (dbits = the bits of nnz - 1)
+//   doff[c*C + j] = offset inside chunk c of the record that goes there: its
+//                   low 16 bits; the offset's higher bits sit in ddst above
+//                   the destination (chunks beyond 65536 records need them)
 // Destinations are distinct (nxt_d is a permutation), so the sorted order is
 // unique and does not depend on how it is computed: sub-runs of kSub records
 // are sorted in LDS, then each chunk's sub-runs are merged by rank.
@@ -29,9 +32,10 @@
 #include "kernels.hpp"
 
 // Bytes of records per chunk (the chunk holds the largest power of two of
-// records that fits, at least kSub and at most 65536 so offsets fit 16 bits).
+// records that fits, at least kSub, and no more than the bits ddst has to
+// spare above the destinations can address).
 #ifndef SPT_STAGE_CHUNK_BYTES
-#define SPT_STAGE_CHUNK_BYTES (1 << 20)
+#define SPT_STAGE_CHUNK_BYTES (2 << 20)
 #endif
 
 namespace spt {
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(kStageThreads) void stage_tables_kernel(const int32
 // destinations are distinct).  Offsets become offsets inside the chunk.
 __global__ __launch_bounds__(kStageThreads) void merge_runs_kernel(const int32_t* __restrict__ sdst,
                                                                    const uint16_t* __restrict__ soff,
-                                                                   int64_t nnz, int cshift,
+                                                                   int64_t nnz, int cshift, int dbits,
                                                                    int32_t* __restrict__ ddst,
                                                                    uint16_t* __restrict__ doff) {
     const int64_t i = blockIdx.x * (int64_t)kStageThreads + threadIdx.x;
@@ -106,8 +110,9 @@ __global__ __launch_bounds__(kStageThreads) void merge_runs_kernel(const int32_t
         }
         pos += lo - rs;
     }
-    ddst[c0 + pos] = key;
-    doff[c0 + pos] = (uint16_t)((r0 - c0) + soff[i]);
+    const uint32_t off = (uint32_t)((r0 - c0) + soff[i]);
+    ddst[c0 + pos] = (int32_t)((uint32_t)key | ((off >> 16) << dbits));
+    doff[c0 + pos] = (uint16_t)(off & 0xFFFFu);
 }
 
 // One record per thread: slot j of the tables, read from its chunk in L2.
@@ -116,7 +121,7 @@ __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_
                                                                     uint32_t* __restrict__ out,
                                                                     const int32_t* __restrict__ ddst,
                                                                     const uint16_t* __restrict__ doff,
-                                                                    int64_t nnz, int cshift) {
+                                                                    int64_t nnz, int cshift, int dbits) {
     constexpr int Q = RW / 4;
     // the grid is a multiple of 8 chunks; block b runs on XCD b % 8 and takes
     // the (b / 8)-th block of that XCD's chunks c = x, x + 8, x + 16, ...
@@ -125,56 +130,62 @@ __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_
     const unsigned v = ((r / bpc) * 8u + x) * bpc + r % bpc;
     const int64_t j = (int64_t)v * kRemapThreads + threadIdx.x;
     if (j >= nnz) return;
-    const int64_t p = ((j >> cshift) << cshift) + doff[j];
-    const int64_t q = ddst[j];
+    const uint32_t t = (uint32_t)ddst[j];
+    const int64_t p = ((j >> cshift) << cshift) + doff[j] + ((int64_t)(t >> dbits) << 16);
+    const int64_t q = t & ((1u << dbits) - 1u);
     const uint4* src = reinterpret_cast<const uint4*>(in);
     uint4* dst = reinterpret_cast<uint4*>(out);
 #pragma unroll
     for (int w = 0; w < Q; ++w) dst[q * Q + w] = src[p * Q + w];
 }
 
-int chunk_shift(int words) {
-    int sh = 16;
-    while (sh > 12 && ((int64_t(1) << sh) * words * 4 > (int64_t)SPT_STAGE_CHUNK_BYTES)) --sh;
+// Bits of a destination (0 .. nnz - 1), at least 1.
+int dest_bits(int64_t nnz) {
+    int b = 1;
+    while (b < 31 && (int64_t(1) << b) < nnz) ++b;
+    return b;
+}
+
+// log2 of the records per chunk: the bytes target, at least kSub, at most
+// what 16 bits of doff and the 32 - dbits spare bits of ddst address.
+int chunk_shift(int words, int64_t nnz) {
+    const int maxsh = 16 + (32 - dest_bits(nnz));
+    int sh = 12;
+    while (sh < maxsh && sh < 24 && ((int64_t(1) << (sh + 1)) * words * 4 <= (int64_t)SPT_STAGE_CHUNK_BYTES)) ++sh;
     return sh;
 }
 
 }  // namespace
 
-int stage_chunk(int words) { return 1 << chunk_shift(words); }
+int stage_chunk(int words, int64_t nnz) { return 1 << chunk_shift(words, nnz); }
 
 void launch_stage_tables(int words, const int32_t* nxt, int64_t nnz, int32_t* ddst, uint16_t* doff,
                          int32_t* tmp_dst, uint16_t* tmp_off, hipStream_t s) {
     if (nnz == 0) return;
-    const int cshift = chunk_shift(words);
-    const bool merge = (1 << cshift) > kSub;
+    const int cshift = chunk_shift(words, nnz);
     const unsigned subs = (unsigned)((nnz + kSub - 1) / kSub);
-    hipLaunchKernelGGL(stage_tables_kernel<kSub>, dim3(subs), dim3(kStageThreads), 0, s, nxt, nnz,
-                       merge ? tmp_dst : ddst, merge ? tmp_off : doff);
-    if (merge) {
-        const unsigned blocks = (unsigned)((nnz + kStageThreads - 1) / kStageThreads);
-        hipLaunchKernelGGL(merge_runs_kernel, dim3(blocks), dim3(kStageThreads), 0, s, (const int32_t*)tmp_dst,
-                           (const uint16_t*)tmp_off, nnz, cshift, ddst, doff);
-    }
+    hipLaunchKernelGGL(stage_tables_kernel<kSub>, dim3(subs), dim3(kStageThreads), 0, s, nxt, nnz, tmp_dst,
+                       tmp_off);
+    const unsigned blocks = (unsigned)((nnz + kStageThreads - 1) / kStageThreads);
+    hipLaunchKernelGGL(merge_runs_kernel, dim3(blocks), dim3(kStageThreads), 0, s, (const int32_t*)tmp_dst,
+                       (const uint16_t*)tmp_off, nnz, cshift, dest_bits(nnz), ddst, doff);
 }
-
-bool stage_tables_need_temp(int words) { return (1 << chunk_shift(words)) > kSub; }
 
 void launch_remap_staged(int words, int64_t nnz, const uint32_t* in, uint32_t* out, const int32_t* ddst,
                          const uint16_t* doff, hipStream_t s) {
     if (nnz == 0) return;
-    const int cshift = chunk_shift(words);
+    const int cshift = chunk_shift(words, nnz), dbits = dest_bits(nnz);
     const int64_t nchunks = (nnz + (int64_t(1) << cshift) - 1) >> cshift;
     const unsigned blocks = (unsigned)(((nchunks + 7) / 8) * 8 * ((int64_t(1) << cshift) / kRemapThreads));
     if (words == 4)
         hipLaunchKernelGGL((remap_flat_kernel<4>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out, ddst, doff,
-                           nnz, cshift);
+                           nnz, cshift, dbits);
     else if (words == 8)
         hipLaunchKernelGGL((remap_flat_kernel<8>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out, ddst, doff,
-                           nnz, cshift);
+                           nnz, cshift, dbits);
     else
         hipLaunchKernelGGL((remap_flat_kernel<12>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out, ddst, doff,
-                           nnz, cshift);
+                           nnz, cshift, dbits);
 }
 
 }  // namespace spt

@@ -68,13 +68,13 @@ void launch_fixup(int rank, const FixupArgs& a, hipStream_t s);
 // following `hops` next-position arrays (nxt[0] first).
 void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,
                   const int32_t* const* nxt, int hops, hipStream_t s);
-// Staged remapping (dr_staged.hip): records in chunks of stage_chunk(words)
-// consecutive stream positions; per chunk, the destinations in increasing
-// order (ddst) and the offset inside the chunk of the record for each (doff).
-// When stage_tables_need_temp(words), the build needs nnz-entry temporaries
-// tmp_dst / tmp_off (otherwise they may be null).
-int stage_chunk(int words);
-bool stage_tables_need_temp(int words);
+// Staged remapping (dr_staged.hip): records in chunks of stage_chunk(words,
+// nnz) consecutive stream positions; per chunk, the destinations in
+// increasing order (ddst) and the offset inside the chunk of the record for
+// each (doff, with the offset's bits above 16 stored in ddst above the
+// destination's bits).  The build needs nnz-entry temporaries tmp_dst /
+// tmp_off.
+int stage_chunk(int words, int64_t nnz);
 void launch_stage_tables(int words, const int32_t* nxt, int64_t nnz, int32_t* ddst, uint16_t* doff,
                          int32_t* tmp_dst, uint16_t* tmp_off, hipStream_t s);
 // out[ddst[j]] = in[chunk(j) * C + doff[j]] for every j < nnz

@@ -357,12 +357,6 @@ def copy_probe(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
                                 _stream(stream)))
 
 
-def stage_chunk(record_bytes: int) -> int:
-    """Records per chunk of the staged remap (opts.dr = 0) for a record size
-    (what spt_info.remap_chunk reports for a handle with that record size)."""
-    return {16: 65536, 32: 32768, 48: 16384}[int(record_bytes)]
-
-
 def tensor_info(t: Tensor) -> Dict[str, object]:
     i = spt_info()
     _check(lib().spt_tensor_info(t.handle, ctypes.byref(i)))

@@ -29,8 +29,7 @@ void launch_fixup(int, const FixupArgs&, hipStream_t) { reached("launch_fixup");
 void launch_remap(int, int64_t, const uint32_t*, uint32_t*, const int32_t* const*, int, hipStream_t) {
     reached("launch_remap");
 }
-int stage_chunk(int) { reached("stage_chunk"); }
-bool stage_tables_need_temp(int) { reached("stage_tables_need_temp"); }
+int stage_chunk(int, int64_t) { reached("stage_chunk"); }
 void launch_stage_tables(int, const int32_t*, int64_t, int32_t*, uint16_t*, int32_t*, uint16_t*, hipStream_t) {
     reached("launch_stage_tables");
 }

@@ -116,7 +116,6 @@ def test_options_reserved_words_must_be_zero_and_remap_forms_map():
     assert [S._opts(0, None, 0, layout=k).layout for k in ("auto", "word32", "half16", "packed")] == [0, 1, 2, 3]
     with pytest.raises(ValueError):
         S._opts(0, None, 0, layout="soa")
-    assert [S.stage_chunk(b) for b in (16, 32, 48)] == [65536, 32768, 16384]
 
 
 def test_struct_layouts_of_the_binding_match_the_header(tmp_path):
