@@ -74,16 +74,23 @@ typedef struct spt_opts {
                            every record at its next position.  The next
                            stream is identical either way                   */
     int32_t layout;     /* record layout of the stream (Sec. 3.5): 0 = chosen
-                           by the library (32-bit indices for N <= 3; 16-bit
-                           fields when every mode has <= 65536 rows; else
-                           bit fields of ceil(log2 I_w) bits; else wider
-                           records); 1 = 32-bit indices (16 / 32 / 48-byte
-                           records for N <= 3 / <= 7 / 8); 2 = 16-bit fields
+                           by the library (the 12-byte record of layout 4
+                           when the indices fit 64 bits; else 32-bit
+                           indices for N <= 3; 16-bit fields when every
+                           mode has <= 65536 rows; else bit fields of
+                           ceil(log2 I_w) bits; else wider records);
+                           1 = 32-bit indices (16 / 32 / 48-byte records
+                           for N <= 3 / <= 7 / 8); 2 = 16-bit fields
                            (N = 4..6: 16 B, N = 8: 32 B; every mode
                            <= 65536 rows); 3 = packed bit fields (N = 4..6,
-                           at most 96 index bits: 16 B).  A layout that does
-                           not fit fails with SPT_ERR_UNSUPPORTED.  Results
-                           are identical for every layout                   */
+                           at most 96 index bits: 16 B); 4 = compact
+                           12-byte records, the indices in 64 bits: 32-bit
+                           indices for N <= 2, 16-bit fields for N = 4
+                           with every mode <= 65536 rows, else packed bit
+                           fields when sum_w ceil(log2 I_w) <= 64.  A
+                           layout that does not fit fails with
+                           SPT_ERR_UNSUPPORTED.  Results are identical for
+                           every layout                                     */
     int32_t reserved;   /* must be zero                                      */
 } spt_opts;
 

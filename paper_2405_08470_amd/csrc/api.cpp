@@ -157,7 +157,7 @@ spt_status get_opts(const spt_opts* o, PlanOptions* po, int* copies, int* dr) {
     if (o->reserved != 0) return fail(SPT_ERR_INVALID_ARG, "opts.reserved must be zero");
     if (o->dr != 0 && o->dr != 1) return fail(SPT_ERR_INVALID_ARG, "opts.dr must be 0 or 1");
     *dr = o->dr;
-    if (o->layout < 0 || o->layout > 3) return fail(SPT_ERR_INVALID_ARG, "opts.layout must be 0..3");
+    if (o->layout < 0 || o->layout > 4) return fail(SPT_ERR_INVALID_ARG, "opts.layout must be 0..4");
     po->layout = o->layout;
     if (o->prep != 0 && o->prep != 1) return fail(SPT_ERR_INVALID_ARG, "opts.prep must be 0 or 1");
     po->prep = o->prep;

@@ -264,9 +264,13 @@ __global__ void pack_kernel(const PackArgs a, const int32_t* __restrict__ order,
             if (sh + a.bits[m] > 32) w[wi + 1] |= (uint32_t)(v >> (32 - sh));
         }
         w[a.words - 1] = __float_as_uint(a.val[e]);
-        uint4* dst = reinterpret_cast<uint4*>(out + p * a.words);
-        for (int k = 0; k < a.words / 4; ++k)
-            dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+        if (a.words % 4 == 0) {
+            uint4* dst = reinterpret_cast<uint4*>(out + p * a.words);
+            for (int k = 0; k < a.words / 4; ++k)
+                dst[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+        } else {
+            for (int k = 0; k < a.words; ++k) out[p * a.words + k] = w[k];
+        }
     }
 }
 

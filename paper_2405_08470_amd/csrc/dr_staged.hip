@@ -30,6 +30,7 @@
 #include <cstdint>
 
 #include "kernels.hpp"
+#include "record.hpp"
 
 // Bytes of records per chunk (the chunk holds the largest power of two of
 // records that fits, at least kSub, and no more than the bits ddst has to
@@ -122,7 +123,6 @@ __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_
                                                                     const int32_t* __restrict__ ddst,
                                                                     const uint16_t* __restrict__ doff,
                                                                     int64_t nnz, int cshift, int dbits) {
-    constexpr int Q = RW / 4;
     // the grid is a multiple of 8 chunks; block b runs on XCD b % 8 and takes
     // the (b / 8)-th block of that XCD's chunks c = x, x + 8, x + 16, ...
     const unsigned bpc = 1u << (cshift - 8);  // workgroups per chunk
@@ -133,10 +133,9 @@ __global__ __launch_bounds__(kRemapThreads) void remap_flat_kernel(const uint32_
     const uint32_t t = (uint32_t)ddst[j];
     const int64_t p = ((j >> cshift) << cshift) + doff[j] + ((int64_t)(t >> dbits) << 16);
     const int64_t q = t & ((1u << dbits) - 1u);
-    const uint4* src = reinterpret_cast<const uint4*>(in);
-    uint4* dst = reinterpret_cast<uint4*>(out);
-#pragma unroll
-    for (int w = 0; w < Q; ++w) dst[q * Q + w] = src[p * Q + w];
+    Rec<RW> rec;
+    load_rec<RW>(in, p, rec);
+    store_rec<RW>(out, q, rec);
 }
 
 // Bits of a destination (0 .. nnz - 1), at least 1.
@@ -177,7 +176,10 @@ void launch_remap_staged(int words, int64_t nnz, const uint32_t* in, uint32_t* o
     const int cshift = chunk_shift(words, nnz), dbits = dest_bits(nnz);
     const int64_t nchunks = (nnz + (int64_t(1) << cshift) - 1) >> cshift;
     const unsigned blocks = (unsigned)(((nchunks + 7) / 8) * 8 * ((int64_t(1) << cshift) / kRemapThreads));
-    if (words == 4)
+    if (words == 3)
+        hipLaunchKernelGGL((remap_flat_kernel<3>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out, ddst, doff,
+                           nnz, cshift, dbits);
+    else if (words == 4)
         hipLaunchKernelGGL((remap_flat_kernel<4>), dim3(blocks), dim3(kRemapThreads), 0, s, in, out, ddst, doff,
                            nnz, cshift, dbits);
     else if (words == 8)

@@ -7,6 +7,7 @@
 #include <utility>
 
 #include "kernels.hpp"
+#include "record.hpp"
 
 namespace spt {
 
@@ -19,25 +20,6 @@ EcFnPtr pick_ec_n7(int, int, int, int, bool);
 EcFnPtr pick_ec_n8(int, int, int, int, bool);
 
 namespace {
-
-template <int RW>
-struct Rec {
-    uint4 q[RW / 4];
-};
-
-template <int RW>
-__device__ __forceinline__ void load_rec(const uint32_t* __restrict__ base, int64_t p, Rec<RW>& r) {
-    const uint4* src = reinterpret_cast<const uint4*>(base + p * RW);
-#pragma unroll
-    for (int k = 0; k < RW / 4; ++k) r.q[k] = src[k];
-}
-
-template <int RW>
-__device__ __forceinline__ void store_rec(uint32_t* __restrict__ base, int64_t p, const Rec<RW>& r) {
-    uint4* dst = reinterpret_cast<uint4*>(base + p * RW);
-#pragma unroll
-    for (int k = 0; k < RW / 4; ++k) dst[k] = r.q[k];
-}
 
 // Split rows: one workgroup per row sums its carry slots.  Thread (q, r)
 // adds slots q, q + Q, q + 2Q, ... of rank r in four interleaved chains,
@@ -200,7 +182,10 @@ void launch_remap(int words, int64_t nnz, const uint32_t* in, uint32_t* out,
     for (int h = 0; h < hops; ++h) ch.nxt[h] = nxt[h];
     const int threads = 256;
     const int64_t blocks = std::min<int64_t>((nnz + threads - 1) / threads, 8192);
-    if (words == 4)
+    if (words == 3)
+        hipLaunchKernelGGL((remap_kernel<3>), dim3((unsigned)blocks), dim3(threads), 0, s, in, out,
+                           nnz, ch, hops);
+    else if (words == 4)
         hipLaunchKernelGGL((remap_kernel<4>), dim3((unsigned)blocks), dim3(threads), 0, s, in, out,
                            nnz, ch, hops);
     else if (words == 8)

@@ -23,6 +23,7 @@
 #include <utility>
 
 #include "kernels.hpp"
+#include "record.hpp"
 
 // float4 gathers a lane keeps in flight (register budget of the batch)
 #ifndef SPT_GATHER_INFLIGHT
@@ -31,32 +32,6 @@
 namespace spt {
 namespace {
 
-template <int RW>
-struct Rec {
-    uint4 q[RW / 4];
-};
-
-template <int W, int RW>
-__device__ __forceinline__ uint32_t rword(const Rec<RW>& r) {
-    static_assert(W < RW, "word");
-    const uint4& v = r.q[W / 4];
-    return (W % 4 == 0) ? v.x : (W % 4 == 1) ? v.y : (W % 4 == 2) ? v.z : v.w;
-}
-
-template <int RW>
-__device__ __forceinline__ void load_rec(const uint32_t* __restrict__ base, int64_t p, Rec<RW>& r) {
-    const uint4* src = reinterpret_cast<const uint4*>(base + p * RW);
-#pragma unroll
-    for (int k = 0; k < RW / 4; ++k) r.q[k] = src[k];
-}
-
-template <int RW>
-__device__ __forceinline__ void store_rec(uint32_t* __restrict__ base, int64_t p, const Rec<RW>& r) {
-    uint4* dst = reinterpret_cast<uint4*>(base + p * RW);
-#pragma unroll
-    for (int k = 0; k < RW / 4; ++k) dst[k] = r.q[k];
-}
-
 // Index of mode W in a record (layout kinds of the planner).
 template <int W, int RW, int KIND>
 __device__ __forceinline__ uint32_t decode(const Rec<RW>& r, const EcArgs& a) {
@@ -64,12 +39,16 @@ __device__ __forceinline__ uint32_t decode(const Rec<RW>& r, const EcArgs& a) {
         return rword<W, RW>(r);
     } else if constexpr (KIND == kHalf16) {
         return (rword<W / 2, RW>(r) >> ((W & 1) * 16)) & 0xFFFFu;
-    } else {  // packed into the first 96 bits of a 16-byte record
+    } else {  // bit fields in the first 64 bits (12-byte record) or 96 bits (16-byte)
         const uint64_t lo = ((uint64_t)rword<1, RW>(r) << 32) | rword<0, RW>(r);
-        const uint64_t hi = rword<2, RW>(r);
         const int o = a.foff[W];
-        const uint64_t x = o >= 64 ? (hi >> (o - 64)) : ((lo >> o) | (o ? (hi << (64 - o)) : 0));
-        return (uint32_t)x & a.fmask[W];
+        if constexpr (RW == 3) {
+            return (uint32_t)(lo >> o) & a.fmask[W];
+        } else {
+            const uint64_t hi = rword<2, RW>(r);
+            const uint64_t x = o >= 64 ? (hi >> (o - 64)) : ((lo >> o) | (o ? (hi << (64 - o)) : 0));
+            return (uint32_t)x & a.fmask[W];
+        }
     }
 }
 
@@ -452,15 +431,24 @@ EcFn pick_rank(int rank, int fdtype, bool reuse) {
 // (record words, layout kind) pairs the planner can choose for N modes
 template <int N>
 EcFn pick_layout(int rank, int fdtype, int words, int kind, bool reuse) {
-    if constexpr (N <= 3) {
+    if constexpr (N <= 2) {
+        if (words == 3 && kind == kWord32) return pick_rank<N, 3, kWord32>(rank, fdtype, reuse);
+        if (words == 4 && kind == kWord32) return pick_rank<N, 4, kWord32>(rank, fdtype, reuse);
+    } else if constexpr (N == 3) {
+        if (words == 3 && kind == kPacked) return pick_rank<N, 3, kPacked>(rank, fdtype, reuse);
         if (words == 4 && kind == kWord32) return pick_rank<N, 4, kWord32>(rank, fdtype, reuse);
     } else if constexpr (N <= 6) {
+        if constexpr (N == 4)
+            if (words == 3 && kind == kHalf16) return pick_rank<N, 3, kHalf16>(rank, fdtype, reuse);
+        if (words == 3 && kind == kPacked) return pick_rank<N, 3, kPacked>(rank, fdtype, reuse);
         if (words == 4 && kind == kHalf16) return pick_rank<N, 4, kHalf16>(rank, fdtype, reuse);
         if (words == 4 && kind == kPacked) return pick_rank<N, 4, kPacked>(rank, fdtype, reuse);
         if (words == 8 && kind == kWord32) return pick_rank<N, 8, kWord32>(rank, fdtype, reuse);
     } else if constexpr (N == 7) {
+        if (words == 3 && kind == kPacked) return pick_rank<N, 3, kPacked>(rank, fdtype, reuse);
         if (words == 8 && kind == kWord32) return pick_rank<N, 8, kWord32>(rank, fdtype, reuse);
     } else {
+        if (words == 3 && kind == kPacked) return pick_rank<N, 3, kPacked>(rank, fdtype, reuse);
         if (words == 8 && kind == kHalf16) return pick_rank<N, 8, kHalf16>(rank, fdtype, reuse);
         if (words == 12 && kind == kWord32) return pick_rank<N, 12, kWord32>(rank, fdtype, reuse);
     }

@@ -7,41 +7,35 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "record.hpp"
 
 namespace spt {
 
 namespace {
 
-template <int RW>
-struct GRec {
-    uint4 q[RW / 4];
-};
-
-template <int W, int RW>
-__device__ __forceinline__ uint32_t gword(const GRec<RW>& r) {
-    const uint4& v = r.q[W / 4];
-    return (W % 4 == 0) ? v.x : (W % 4 == 1) ? v.y : (W % 4 == 2) ? v.z : v.w;
-}
-
 template <int W, int RW, int KIND>
-__device__ __forceinline__ uint32_t gdecode(const GRec<RW>& r, const int32_t* foff,
+__device__ __forceinline__ uint32_t gdecode(const Rec<RW>& r, const int32_t* foff,
                                             const uint32_t* fmask) {
     if constexpr (KIND == kWord32) {
-        return gword<W, RW>(r);
+        return rword<W, RW>(r);
     } else if constexpr (KIND == kHalf16) {
-        return (gword<W / 2, RW>(r) >> ((W & 1) * 16)) & 0xFFFFu;
+        return (rword<W / 2, RW>(r) >> ((W & 1) * 16)) & 0xFFFFu;
     } else {
-        const uint64_t lo = ((uint64_t)gword<1, RW>(r) << 32) | gword<0, RW>(r);
-        const uint64_t hi = gword<2, RW>(r);
+        const uint64_t lo = ((uint64_t)rword<1, RW>(r) << 32) | rword<0, RW>(r);
         const int o = foff[W];
-        const uint64_t x = o >= 64 ? (hi >> (o - 64)) : ((lo >> o) | (o ? (hi << (64 - o)) : 0));
-        return (uint32_t)x & fmask[W];
+        if constexpr (RW == 3) {
+            return (uint32_t)(lo >> o) & fmask[W];
+        } else {
+            const uint64_t hi = rword<2, RW>(r);
+            const uint64_t x = o >= 64 ? (hi >> (o - 64)) : ((lo >> o) | (o ? (hi << (64 - o)) : 0));
+            return (uint32_t)x & fmask[W];
+        }
     }
 }
 
 // Product over modes of the lane's 4 ranks of each gathered row.
 template <int N, int R, int RW, int KIND, int W>
-__device__ __forceinline__ void mult_rows(const GRec<RW>& r, const ForwardArgs& a, int li,
+__device__ __forceinline__ void mult_rows(const Rec<RW>& r, const ForwardArgs& a, int li,
                                           float (&p)[4]) {
     if constexpr (W < N) {
         const uint32_t c = gdecode<W, RW, KIND>(r, a.foff, a.fmask);
@@ -65,23 +59,19 @@ __global__ __launch_bounds__(256) void forward_kernel(const ForwardArgs a) {
     const int g = tid / L, li = tid % L;
     double loss = 0.0;
     for (int64_t p = (int64_t)blockIdx.x * GPB + g; p < a.nnz; p += (int64_t)gridDim.x * GPB) {
-        GRec<RW> r;
-        const uint4* src = reinterpret_cast<const uint4*>(a.rec_in + p * RW);
-#pragma unroll
-        for (int k = 0; k < RW / 4; ++k) r.q[k] = src[k];
+        Rec<RW> r;
+        load_rec<RW>(a.rec_in, p, r);
         float prod[4] = {1.f, 1.f, 1.f, 1.f};
         mult_rows<N, R, RW, KIND, 0>(r, a, li, prod);
         float m = (prod[0] + prod[1]) + (prod[2] + prod[3]);
 #pragma unroll
         for (int off = 1; off < L; off <<= 1) m += __shfl_xor(m, off, L);
-        const float x = __uint_as_float(gword<RW - 1, RW>(r));
+        const float x = __uint_as_float(rword<RW - 1, RW>(r));
         const float res = m - x;
         if (li == 0) {
-            GRec<RW> o = r;
-            o.q[RW / 4 - 1].w = __float_as_uint(res);
-            uint4* dst = reinterpret_cast<uint4*>(a.rec_res + p * RW);
-#pragma unroll
-            for (int k = 0; k < RW / 4; ++k) dst[k] = o.q[k];
+            Rec<RW> o = r;
+            o.w[RW - 1] = __float_as_uint(res);
+            store_rec<RW>(a.rec_res, p, o);
             loss += 0.5 * (double)res * (double)res;
         }
     }
@@ -107,15 +97,24 @@ bool fwd_rank(int rank, int blocks, const ForwardArgs& a, hipStream_t s) {
 
 template <int N>
 bool fwd_layout(int rank, int words, int kind, int blocks, const ForwardArgs& a, hipStream_t s) {
-    if constexpr (N <= 3) {
+    if constexpr (N <= 2) {
+        if (words == 3 && kind == kWord32) return fwd_rank<N, 3, kWord32>(rank, blocks, a, s);
+        if (words == 4 && kind == kWord32) return fwd_rank<N, 4, kWord32>(rank, blocks, a, s);
+    } else if constexpr (N == 3) {
+        if (words == 3 && kind == kPacked) return fwd_rank<N, 3, kPacked>(rank, blocks, a, s);
         if (words == 4 && kind == kWord32) return fwd_rank<N, 4, kWord32>(rank, blocks, a, s);
     } else if constexpr (N <= 6) {
+        if constexpr (N == 4)
+            if (words == 3 && kind == kHalf16) return fwd_rank<N, 3, kHalf16>(rank, blocks, a, s);
+        if (words == 3 && kind == kPacked) return fwd_rank<N, 3, kPacked>(rank, blocks, a, s);
         if (words == 4 && kind == kHalf16) return fwd_rank<N, 4, kHalf16>(rank, blocks, a, s);
         if (words == 4 && kind == kPacked) return fwd_rank<N, 4, kPacked>(rank, blocks, a, s);
         if (words == 8 && kind == kWord32) return fwd_rank<N, 8, kWord32>(rank, blocks, a, s);
     } else if constexpr (N == 7) {
+        if (words == 3 && kind == kPacked) return fwd_rank<N, 3, kPacked>(rank, blocks, a, s);
         if (words == 8 && kind == kWord32) return fwd_rank<N, 8, kWord32>(rank, blocks, a, s);
     } else {
+        if (words == 3 && kind == kPacked) return fwd_rank<N, 3, kPacked>(rank, blocks, a, s);
         if (words == 8 && kind == kHalf16) return fwd_rank<N, 8, kHalf16>(rank, blocks, a, s);
         if (words == 12 && kind == kWord32) return fwd_rank<N, 12, kWord32>(rank, blocks, a, s);
     }

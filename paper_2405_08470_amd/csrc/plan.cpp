@@ -302,8 +302,23 @@ bool choose_layout(int nmodes, const int64_t* dims, int pref, RecordLayout* lay)
         }
     };
     if (nmodes < 1 || nmodes > kMaxModes) return false;
+    // 12-byte records: the indices in the first 64 bits, in the cheapest
+    // decode that fits (whole words, 16-bit fields, else bit fields)
+    auto compact = [&]() {
+        if (nmodes <= 2)
+            set(kWord32, 3);
+        else if (nmodes == 4 && small)
+            set(kHalf16, 3);
+        else if (packed_bits <= 64)
+            set(kPacked, 3);
+        else
+            return false;
+        return true;
+    };
     const int word32_words = nmodes <= 3 ? 4 : nmodes <= 7 ? 8 : 12;
     switch (pref) {
+        case kLayoutCompact:
+            return compact();
         case kLayoutWord32:
             set(kWord32, word32_words);
             return true;
@@ -319,6 +334,8 @@ bool choose_layout(int nmodes, const int64_t* dims, int pref, RecordLayout* lay)
         default:
             break;
     }
+    if (compact())
+        return true;
     if (nmodes <= 3)
         set(kWord32, 4);
     else if (small && nmodes <= 6)

@@ -105,7 +105,7 @@ void build_plan(int nmodes, const int64_t* dims, int64_t nnz, const int32_t* idx
 // Chooses the smallest record, preferring layouts the kernels decode with
 // fixed shifts; returns false if no layout fits.
 // Record layout preference (spt_opts.layout): automatic, or one kind forced.
-enum { kLayoutAuto = 0, kLayoutWord32 = 1, kLayoutHalf16 = 2, kLayoutPacked = 3 };
+enum { kLayoutAuto = 0, kLayoutWord32 = 1, kLayoutHalf16 = 2, kLayoutPacked = 3, kLayoutCompact = 4 };
 // false if the preferred kind has no kernel for this mode count or these dims
 bool choose_layout(int nmodes, const int64_t* dims, int pref, RecordLayout* lay);
 

@@ -109,7 +109,7 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(int(stream))
 
 
-LAYOUTS = {"auto": 0, "word32": 1, "half16": 2, "packed": 3}
+LAYOUTS = {"auto": 0, "word32": 1, "half16": 2, "packed": 3, "compact": 4}
 
 
 def _opts(kappa: int, split_cap: Optional[int], copies: int, prep: str = "host",
@@ -178,7 +178,7 @@ def tensor_load_coo(dims, indices, values, kappa: int = 0, split_cap: Optional[i
     """prep: "host" (planner threads) or "device" (planner kernels).
     remap: "staged" (a remap pass after the elementwise kernel) or "fused"
     (the elementwise kernel stores each record at its next position).
-    layout: "auto", "word32", "half16" or "packed" (record layout)."""
+    layout: "auto", "word32", "half16", "packed" or "compact" (record layout)."""
     dims64, idx, val = _host_coo(dims, indices, values)
     out = ctypes.c_void_p()
     o = _opts(kappa, split_cap, copies, prep, remap, layout)

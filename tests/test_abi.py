@@ -83,8 +83,8 @@ def test_planner_rejects_bad_input(dims, idx, name):
     ("dr", -1, "opts.dr must be 0 or 1"),
     ("prep", 2, "opts.prep must be 0 or 1"),
     ("copies", 3, "opts.copies must be 0 or 1"),
-    ("layout", 4, "opts.layout must be 0..3"),
-    ("layout", -1, "opts.layout must be 0..3"),
+    ("layout", 5, "opts.layout must be 0..4"),
+    ("layout", -1, "opts.layout must be 0..4"),
 ])
 def test_options_are_validated_before_any_device_work(field, value, msg):
     import ctypes
@@ -113,7 +113,7 @@ def test_options_reserved_words_must_be_zero_and_remap_forms_map():
     assert S._opts(0, None, 0, remap="fused").dr == 1
     with pytest.raises(ValueError):
         S._opts(0, None, 0, remap="pull")
-    assert [S._opts(0, None, 0, layout=k).layout for k in ("auto", "word32", "half16", "packed")] == [0, 1, 2, 3]
+    assert [S._opts(0, None, 0, layout=k).layout for k in ("auto", "word32", "half16", "packed", "compact")] == [0, 1, 2, 3, 4]
     with pytest.raises(ValueError):
         S._opts(0, None, 0, layout="soa")
 

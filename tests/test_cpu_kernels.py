@@ -100,10 +100,10 @@ from paper_2405_08470_amd.spmttkrp import spt_info as Info, spt_opts as Opts  # 
 class T:
     """A tensor loaded into the CPU build."""
 
-    def __init__(self, L, dims, idx, val, kappa=0, split_cap=None, copies=0, dr=0):
+    def __init__(self, L, dims, idx, val, kappa=0, split_cap=None, copies=0, dr=0, layout=0):
         self.L, self.dims, self.N, self.nnz = L, tuple(dims), len(dims), idx.shape[1]
         o = Opts()
-        o.kappa, o.copies, o.dr = kappa, copies, dr
+        o.kappa, o.copies, o.dr, o.layout = kappa, copies, dr, layout
         o.split_cap = 0 if split_cap is None else (split_cap if split_cap > 0 else -1)
         self._d = np.ascontiguousarray(dims, dtype=np.int64)
         self._i = np.ascontiguousarray(idx, dtype=np.int32)
@@ -147,27 +147,35 @@ def bf16_bits(y):
     return (oracle.bf16_round(y).view(np.uint32) >> 16).astype(np.uint16)
 
 
+LAYOUTS = {"auto": 0, "word32": 1, "half16": 2, "packed": 3, "compact": 4}
 CASES = [
-    # name, dims, nnz, dist, zipf_s, R, kappa, split_cap
-    ("zipf3_r32", (300, 250, 6000), 30_000, "zipf", 1.1, 32, 0, None),
-    ("zipf5_r32", (100, 100, 50, 20, 5), 20_000, "zipf", 1.2, 32, 97, None),
-    ("zipf4_r64", (500, 500, 200, 10), 15_000, "zipf", 1.1, 64, 0, None),
-    ("zipf3_r8", (400, 300, 200), 15_000, "zipf", 1.3, 8, 13, None),
-    ("zipf3_r128", (400, 300, 200), 5_000, "zipf", 1.1, 128, 0, None),
-    ("zipf2_nosplit", (500, 400), 15_000, "zipf", 1.5, 16, 31, 0),
-    ("zipf8_r16", (9, 8, 7, 6, 5, 4, 3, 2), 4_000, "zipf", 1.1, 16, 5, None),
-    ("uniform3_r16", (60, 50, 40), 8_000, "uniform", 1.1, 16, 0, None),
-    # more than two remap chunks of 65536 records, the last one partial
-    ("zipf3_chunks", (400, 300, 2000), 140_000, "zipf", 1.1, 8, 0, None),
+    # name, dims, nnz, dist, zipf_s, R, kappa, split_cap, layout (auto: the
+    # 12-byte records wherever the indices fit 64 bits)
+    ("zipf3_r32", (300, 250, 6000), 30_000, "zipf", 1.1, 32, 0, None, "auto"),
+    ("zipf5_r32", (100, 100, 50, 20, 5), 20_000, "zipf", 1.2, 32, 97, None, "auto"),
+    ("zipf4_r64", (500, 500, 200, 10), 15_000, "zipf", 1.1, 64, 0, None, "auto"),
+    ("zipf3_r8", (400, 300, 200), 15_000, "zipf", 1.3, 8, 13, None, "auto"),
+    ("zipf3_r128", (400, 300, 200), 5_000, "zipf", 1.1, 128, 0, None, "auto"),
+    ("zipf2_nosplit", (500, 400), 15_000, "zipf", 1.5, 16, 31, 0, "auto"),
+    ("zipf8_r16", (9, 8, 7, 6, 5, 4, 3, 2), 4_000, "zipf", 1.1, 16, 5, None, "auto"),
+    ("uniform3_r16", (60, 50, 40), 8_000, "uniform", 1.1, 16, 0, None, "auto"),
+    # 16-byte and wider records
+    ("zipf3_r32_word32", (300, 250, 6000), 30_000, "zipf", 1.1, 32, 0, None, "word32"),
+    ("zipf5_r32_half16", (100, 100, 50, 20, 5), 20_000, "zipf", 1.2, 32, 97, None, "half16"),
+    ("zipf4_r64_packed", (500, 500, 200, 10), 15_000, "zipf", 1.1, 64, 0, None, "packed"),
+    ("zipf8_r16_half16", (9, 8, 7, 6, 5, 4, 3, 2), 4_000, "zipf", 1.1, 16, 5, None, "half16"),
+    # two remap chunks of 131072 records, the last one partial
+    ("zipf3_chunks", (400, 300, 2000), 140_000, "zipf", 1.1, 8, 0, None, "auto"),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_all_modes_with_remap_against_the_oracle(lib, case):
-    name, dims, nnz, dist, s, R, kappa, cap = case
+    name, dims, nnz, dist, s, R, kappa, cap, layout = case
     idx, val = synth.random_coo(dims, nnz, seed=17, dist=dist, zipf_s=s)
     Y = synth.random_factors(dims, R, seed=18)
-    t = T(lib, dims, idx, val, kappa=kappa, split_cap=cap)
+    t = T(lib, dims, idx, val, kappa=kappa, split_cap=cap, layout=LAYOUTS[layout])
+    assert t.info().record_bytes == (12 if layout == "auto" else 16 if len(dims) <= 6 else 32), name
     plan = oracle.plan(dims, idx, t.info().kappa, split_cap=cap)
     N = len(dims)
     for d in range(N):

@@ -45,10 +45,16 @@ def _passes(dims, idx, val, R, Y, layout, prep):
 
 CASES = [
     # name, dims, nnz, R, {layout: record bytes}
-    ("4mode", (3000, 2500, 1000, 60), 120_000, 16, {"half16": 16, "packed": 16, "word32": 32}),
-    ("5mode", (1000, 1000, 500, 200, 50), 100_000, 32, {"half16": 16, "packed": 16, "word32": 32}),
-    ("6mode_big", (70_000, 300, 200, 40, 30, 20), 60_000, 8, {"packed": 16, "word32": 32}),
-    ("8mode", (9, 8, 7, 6, 5, 4, 3, 2), 20_000, 8, {"half16": 32, "word32": 48}),
+    ("2mode", (5000, 4000), 60_000, 16, {"compact": 12, "word32": 16}),
+    ("3mode", (100_000, 80_000, 3000), 100_000, 32, {"compact": 12, "word32": 16}),
+    ("4mode", (3000, 2500, 1000, 60), 120_000, 16,
+     {"compact": 12, "half16": 16, "packed": 16, "word32": 32}),
+    ("4mode_big", (70_000, 2500, 1000, 60), 80_000, 16, {"compact": 12, "packed": 16, "word32": 32}),
+    ("5mode", (1000, 1000, 500, 200, 50), 100_000, 32,
+     {"compact": 12, "half16": 16, "packed": 16, "word32": 32}),
+    ("6mode_big", (70_000, 300, 200, 40, 30, 20), 60_000, 8, {"compact": 12, "packed": 16, "word32": 32}),
+    ("7mode", (9, 8, 7, 6, 5, 4, 3), 20_000, 8, {"compact": 12, "word32": 32}),
+    ("8mode", (9, 8, 7, 6, 5, 4, 3, 2), 20_000, 8, {"compact": 12, "half16": 32, "word32": 48}),
 ]
 
 
@@ -84,7 +90,9 @@ def test_layouts_give_identical_results(name, dims, nnz, R, layouts):
     ((50, 40, 30), "packed"),
     ((9, 8, 7, 6, 5, 4, 3), "half16"),          # 7 modes: 32-bit indices only
     ((70_000, 30, 20, 10), "half16"),           # a mode with more than 65536 rows
-    ((9, 8, 7, 6, 5, 4, 3, 2), "packed"),       # packed fields: 4..6 modes
+    ((9, 8, 7, 6, 5, 4, 3, 2), "packed"),       # 16-byte packed fields: 4..6 modes
+    ((3_000_000, 3_000_000, 3_000_000), "compact"),  # 66 index bits
+    ((70_000, 70_000, 70_000, 70_000), "compact"),   # 68 index bits
 ])
 def test_layout_that_does_not_fit_is_refused(dims, layout):
     idx, val = synth.random_coo(dims, 500, seed=3, dist="uniform")

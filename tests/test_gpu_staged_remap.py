@@ -6,7 +6,8 @@ opts.dr = 1 stores every record at its next position from inside the
 elementwise kernel.  Both must leave the same next-mode stream, bit for bit
 (integer work), and the MTTKRP outputs must be bit-identical (the elementwise
 kernel reads the same stream in the same order).  Cases cover every record
-width (16, 32, 48 bytes, i.e. chunks of 131072, 65536, 32768 records, each
+width (12, 16, 32, 48 bytes, i.e. chunks of 131072, 131072, 65536, 32768
+records, each
 sorted as runs of 4096 that are then merged, offsets past 16 bits stored
 above the destination), a partial last chunk, an exact multiple of the
 chunk, a chunk plus one record, two runs in one partial chunk, one nonzero,
@@ -35,20 +36,25 @@ def _say(*a):
 
 
 CASES = [
-    # name, dims, nnz, R, record bytes
-    ("w16_tail", (3000, 2500, 60_000), 250_001, 32, 16),
-    ("w16_exact", (500, 400, 300), 131072 * 2, 16, 16),
-    ("w16_chunk_plus_one", (300, 200, 100), 131072 + 1, 8, 16),
-    ("w16_two_runs", (300, 200, 100), 4097, 8, 16),
-    ("w16_5mode", (1000, 1000, 500, 200, 50), 120_000, 16, 16),
-    ("w32_8mode", (20, 20, 20, 20, 20, 20, 20, 20), 50_000, 8, 32),
-    ("w48_8mode", (70_000, 5, 5, 5, 5, 5, 5, 5), 30_000, 8, 48),
-    ("one", (10, 10, 10), 1, 8, 16),
+    # name, dims, nnz, R, layout, record bytes
+    ("w12_tail", (3000, 2500, 60_000), 250_001, 32, "auto", 12),
+    ("w12_exact", (500, 400, 300), 131072 * 2, 16, "auto", 12),
+    ("w12_chunk_plus_one", (300, 200, 100), 131072 + 1, 8, "auto", 12),
+    ("w12_4mode_half16", (3000, 2500, 1000, 60), 140_000, 16, "auto", 12),
+    ("w12_2mode", (5000, 4000), 60_000, 8, "auto", 12),
+    ("w16_tail", (3000, 2500, 60_000), 250_001, 32, "word32", 16),
+    ("w16_exact", (500, 400, 300), 131072 * 2, 16, "word32", 16),
+    ("w16_chunk_plus_one", (300, 200, 100), 131072 + 1, 8, "word32", 16),
+    ("w16_two_runs", (300, 200, 100), 4097, 8, "word32", 16),
+    ("w16_5mode", (1000, 1000, 500, 200, 50), 120_000, 16, "half16", 16),
+    ("w32_8mode", (20, 20, 20, 20, 20, 20, 20, 20), 50_000, 8, "half16", 32),
+    ("w48_8mode", (70_000, 5, 5, 5, 5, 5, 5, 5), 30_000, 8, "word32", 48),
+    ("one", (10, 10, 10), 1, 8, "auto", 12),
 ]
 
 
-def _run(dims, idx, val, R, remap, prep, Y):
-    t = S.tensor_load_coo(dims, idx, val, remap=remap, prep=prep)
+def _run(dims, idx, val, R, remap, prep, Y, layout):
+    t = S.tensor_load_coo(dims, idx, val, remap=remap, prep=prep, layout=layout)
     f = [torch.from_numpy(y).cuda() for y in Y]
     streams, outs = [], []
     for d in range(len(dims)):
@@ -64,13 +70,13 @@ def _run(dims, idx, val, R, remap, prep, Y):
     return streams, outs, info
 
 
-@pytest.mark.parametrize("name,dims,nnz,R,rb", CASES, ids=[c[0] for c in CASES])
-def test_staged_remap_equals_fused_remap(name, dims, nnz, R, rb):
+@pytest.mark.parametrize("name,dims,nnz,R,layout,rb", CASES, ids=[c[0] for c in CASES])
+def test_staged_remap_equals_fused_remap(name, dims, nnz, R, layout, rb):
     _say("case", name, dims, nnz)
     idx, val = synth.random_coo(dims, nnz, seed=nnz % 1000, dist="zipf", zipf_s=1.1)
     Y = synth.random_factors(dims, R, seed=4)
-    s_st, o_st, i_st = _run(dims, idx, val, R, "staged", "host", Y)
-    s_fu, o_fu, i_fu = _run(dims, idx, val, R, "fused", "device", Y)
+    s_st, o_st, i_st = _run(dims, idx, val, R, "staged", "host", Y, layout)
+    s_fu, o_fu, i_fu = _run(dims, idx, val, R, "fused", "device", Y, layout)
     assert i_st["record_bytes"] == i_fu["record_bytes"] == rb
     # a power of two of at least 4096 records; the fused form has no pass
     ch = i_st["remap_chunk"]
