@@ -60,8 +60,8 @@ def log(*a):
 CSRC = "paper_2405_08470_amd/csrc/"
 # kernel family -> sources the kernel is built from (for the profile match)
 SOURCES = {
-    "ec_kernel": (CSRC + "ec_kernel.hpp", CSRC + "ec_kernel.hip", CSRC + "kernels.hpp"),
-    "remap_flat_kernel": (CSRC + "dr_staged.hip", CSRC + "kernels.hpp"),
+    "ec_kernel": (CSRC + "ec_kernel.hpp", CSRC + "ec_kernel.hip", CSRC + "kernels.hpp", CSRC + "record.hpp"),
+    "remap_flat_kernel": (CSRC + "dr_staged.hip", CSRC + "kernels.hpp", CSRC + "record.hpp"),
 }
 
 
@@ -442,8 +442,8 @@ def oracle_leg(keep, budget_s, want_accuracy):
 def ablation(torch, S, synth, name, K, W, kappa0):
     """The all-mode pass across partition counts kappa (the analog of the
     paper's threadblock-count sweep, Sec. 5.5), with the remap fused into the
-    elementwise kernel, with the heavy-row split off (pure Alg. 1), and, for
-    four modes or more, with each record layout (Sec. 3.5): ms per pass,
+    elementwise kernel, with the heavy-row split off (pure Alg. 1), and with
+    each wider record layout (Sec. 3.5): ms per pass,
     per-mode kernel times, largest partition."""
     spec = synth.WORKLOADS[name]
     dims, idx, val = synth.make_coo(spec)
@@ -454,10 +454,11 @@ def ablation(torch, S, synth, name, K, W, kappa0):
     rows = []
     settings = [(k, None, "staged", "auto") for k in (2048, 4096, 8192, 16384, 32768, 65536)]
     settings += [(8192, None, "fused", "auto"), (8192, 0, "staged", "auto")]
-    if N >= 4:
-        small = max(dims) <= 65536
-        lays = (["half16"] if small and N != 7 else []) + (["packed"] if N <= 6 else []) + ["word32"]
-        settings += [(8192, None, "staged", lay) for lay in lays]
+    # the wider layouts beside the automatic choice (12-byte records where
+    # the indices fit 64 bits)
+    small = max(dims) <= 65536
+    lays = (["half16"] if small and (4 <= N <= 6 or N == 8) else []) + (["packed"] if 4 <= N <= 6 else []) + ["word32"]
+    settings += [(8192, None, "staged", lay) for lay in lays]
     for kappa, cap, remap, layout in settings:
         t = S.tensor_load_coo(dims, idx, val, kappa=kappa, split_cap=cap, prep="device", remap=remap,
                               layout=layout)

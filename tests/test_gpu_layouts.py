@@ -1,6 +1,7 @@
 """Record layouts (Sec. 3.5: how a nonzero's indices are stored) against each
 other on the GPU: 32-bit index words, 16-bit fields and packed bit fields of
-ceil(log2 I_w) bits.  The layout changes only how indices are decoded, so the
+ceil(log2 I_w) bits, in 16-byte (or wider) records and in the compact
+12-byte record (the indices in 64 bits), 2 to 8 modes.  The layout changes only how indices are decoded, so the
 streams must unpack to the same records and the MTTKRP outputs must be
 bit-identical across layouts, and equal to the oracle within 1e-5.  Layouts
 that do not fit a shape are refused with SPT_ERR_UNSUPPORTED, by both
