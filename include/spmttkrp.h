@@ -65,9 +65,10 @@ typedef struct spt_opts {
     int32_t dr;         /* how a remapping MTTKRP moves the stream to the next
                            mode's order (Alg. 3), copies == 0 only:
                            0 = a second pass after the elementwise kernel
-                           that writes each chunk of 2 MB of consecutive
-                           records (131072 16-byte records; fewer when the
-                           tables cannot address that many: see
+                           that writes each chunk of consecutive records
+                           (the largest power of two of records within
+                           2 MB: 131072 records of 12 or 16 bytes; fewer
+                           when the tables cannot address that many: see
                            spt_info.remap_chunk) in destination order; the
                            load builds its tables, 6 bytes per nonzero and
                            mode.  1 = fused: the elementwise kernel stores

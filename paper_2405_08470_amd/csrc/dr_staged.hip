@@ -2,9 +2,10 @@
 // order.
 //
 // The fused form stores each record at its next-mode position while the
-// elementwise computation runs (one 16-byte store to a random address per
-// nonzero).  Here the stream is cut into chunks of C consecutive records (2 MB
-// of records: 131072 16-byte records), and the records of each chunk are
+// elementwise computation runs (one 12- or 16-byte store to a random address
+// per nonzero).  Here the stream is cut into chunks of C consecutive records
+// (the largest power of two of records within 2 MB: 131072 records of 12 or
+// 16 bytes), and the records of each chunk are
 // written in the order of their destinations: consecutive threads take
 // consecutive table slots, so records of one chunk that land next to each
 // other in the next mode's stream go out in the same store instruction and

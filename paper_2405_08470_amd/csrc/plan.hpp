@@ -16,12 +16,14 @@ constexpr int kMaxModes = 8;
 //   kWord32  index w is word w                      (N <= words - 1)
 //   kHalf16  index w is the half-word w (dims <= 2^16)
 //   kPacked  indices packed back to back, each ceil(log2 I_w) bits, in the
-//            first 96 bits (16-byte records only)
+//            first 64 bits (12-byte records) or 96 bits (16-byte records)
+// A 12-byte record (words = 3) holds its indices in 64 bits: kWord32 for
+// N <= 2, kHalf16 for N = 4, kPacked otherwise.
 enum LayoutKind : int { kWord32 = 0, kHalf16 = 1, kPacked = 2 };
 
 struct RecordLayout {
     int nmodes = 0;
-    int words = 0;            // 4 (16 B), 8 (32 B) or 12 (48 B)
+    int words = 0;            // 3 (12 B), 4 (16 B), 8 (32 B) or 12 (48 B)
     int kind = kWord32;
     int bits[kMaxModes] = {};
     int off[kMaxModes] = {};
