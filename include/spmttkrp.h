@@ -19,6 +19,8 @@
  *  - Indices are 0-based int32, values FP32.  Dimensions and nnz must be
  *    below 2^31; 2 <= nmodes <= 8.  Ranks 8, 16, 32, 64 and 128 are compiled.
  *  - Factor matrices are row-major I_w x R, FP32 or BF16 (spt_dtype).
+ *    Factor, output and gradient matrices must start on a 16-byte boundary
+ *    (rows are moved as 16-byte vectors); INVALID_ARG otherwise.
  */
 #ifndef SPMTTKRP_H
 #define SPMTTKRP_H

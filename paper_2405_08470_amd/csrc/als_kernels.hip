@@ -308,7 +308,10 @@ __global__ __launch_bounds__(256) void solve_rows_mfma_kernel(const float* __res
     const int64_t tiles = (rows + 15) / 16;
     for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < tiles; tile += (int64_t)gridDim.x * 4) {
         const int64_t r0 = tile * 16;
+        // every load of the tile is issued before any of it is used: the
+        // lane's A values, and M at the lane's result positions for <M, Y>
         float av[KS];
+        float mv[CT][4];
         const int64_t ra = r0 + rl;
         if (ra < rows) {
             const float4* src = reinterpret_cast<const float4*>(M + ra * R + q * KS);
@@ -323,6 +326,12 @@ __global__ __launch_bounds__(256) void solve_rows_mfma_kernel(const float* __res
         } else {
 #pragma unroll
             for (int j = 0; j < KS; ++j) av[j] = 0.0f;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = r0 + 4 * v + q;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) mv[ct][v] = row < rows ? M[row * R + 16 * ct + rl] : 0.0f;
         }
         v4d acc[CT];
 #pragma unroll
@@ -344,7 +353,7 @@ __global__ __launch_bounds__(256) void solve_rows_mfma_kernel(const float* __res
                     const float yf = (float)acc[ct][v];
                     Y[row * R + col] = yf;
                     y = (double)yf;
-                    iacc[ct] += (double)M[row * R + col] * y;
+                    iacc[ct] += (double)mv[ct][v] * y;
                 }
                 yd[ct][v] = y;
             }
@@ -496,14 +505,24 @@ __global__ __launch_bounds__(256) void als_finish_kernel(const double* __restric
     }
 }
 
+// Y(i, c) / lambda_c in FP64, rounded once; 4 columns (one 16-byte word) per
+// thread, the grid covering the matrix in one sweep where it can.
 template <int R>
 __global__ void scale_cols_kernel(float* __restrict__ Y, int64_t rows,
                                   const double* __restrict__ lambda) {
-    const int64_t total = rows * R;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+    static_assert(R % 4 == 0, "rank");
+    const int64_t total4 = rows * (R / 4);
+    float4* Y4 = reinterpret_cast<float4*>(Y);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total4;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double l = lambda[i % R];
-        Y[i] = l > 0.0 ? (float)((double)Y[i] / l) : 0.0f;
+        const int c = (int)(i % (R / 4)) * 4;
+        float4 y = Y4[i];
+        const double l0 = lambda[c], l1 = lambda[c + 1], l2 = lambda[c + 2], l3 = lambda[c + 3];
+        y.x = l0 > 0.0 ? (float)((double)y.x / l0) : 0.0f;
+        y.y = l1 > 0.0 ? (float)((double)y.y / l1) : 0.0f;
+        y.z = l2 > 0.0 ? (float)((double)y.z / l2) : 0.0f;
+        y.w = l3 > 0.0 ? (float)((double)y.w / l3) : 0.0f;
+        Y4[i] = y;
     }
 }
 
@@ -578,9 +597,9 @@ void launch_als_finish(int rank, int nmodes, int mode, const double* Gun, const 
 }
 
 void launch_scale_cols(int rank, float* Y, int64_t rows, const double* lambda, hipStream_t s) {
-    const int64_t total = rows * rank;
-    if (total == 0) return;
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+    const int64_t total4 = rows * (rank / 4);
+    if (total4 == 0) return;
+    const int64_t blocks = std::min<int64_t>((total4 + 255) / 256, int64_t(1) << 20);
     by_rank<Scale>(rank, dim3((unsigned)blocks), dim3(256), s, Y, rows, lambda);
 }
 

@@ -41,6 +41,8 @@ spt_status hip_fail(hipError_t e, const char* what) {
 
 bool rank_compiled(int r) { return r == 8 || r == 16 || r == 32 || r == 64 || r == 128; }
 bool als_rank(int r) { return r == 8 || r == 16 || r == 32 || r == 64; }
+// factor rows and output rows move as 16-byte vectors
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 }  // namespace
 
@@ -744,6 +746,9 @@ spt_status spt_mttkrp(spt_tensor_t t, int32_t mode, const void* const* factors, 
     if (!factors || !out) return fail(SPT_ERR_INVALID_ARG, "NULL factors or out");
     for (int w = 0; w < t->N; ++w)
         if (w != mode && !factors[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor matrix");
+    for (int w = 0; w < t->N; ++w)
+        if (w != mode && !aligned16(factors[w])) return fail(SPT_ERR_INVALID_ARG, "factor matrices must be 16-byte aligned");
+    if (!aligned16(out)) return fail(SPT_ERR_INVALID_ARG, "out must be 16-byte aligned");
     if (flags & ~(SPT_FUSE_REMAP_NEXT | SPT_AUTO_REMAP)) return fail(SPT_ERR_INVALID_ARG, "unknown flag");
     hipStream_t s = (hipStream_t)stream;
     if (!t->copies && t->cur_mode != mode) {
@@ -766,6 +771,9 @@ spt_status spt_mttkrp_noalloc(spt_tensor_t t, int32_t mode, const void* const* f
     if (!factors || !out) return fail(SPT_ERR_INVALID_ARG, "NULL factors or out");
     for (int w = 0; w < t->N; ++w)
         if (w != mode && !factors[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor matrix");
+    for (int w = 0; w < t->N; ++w)
+        if (w != mode && !aligned16(factors[w])) return fail(SPT_ERR_INVALID_ARG, "factor matrices must be 16-byte aligned");
+    if (!aligned16(out)) return fail(SPT_ERR_INVALID_ARG, "out must be 16-byte aligned");
     if (flags & ~(SPT_FUSE_REMAP_NEXT | SPT_AUTO_REMAP)) return fail(SPT_ERR_INVALID_ARG, "unknown flag");
     const int64_t need = (int64_t)t->nslots[mode] * rank * 4;
     if (need > spt::kNoAllocScratchBytes)
@@ -804,6 +812,8 @@ spt_status spt_cp_als_iter(spt_tensor_t t, void* const* factors, spt_dtype fdtyp
     if (!factors || !lambda) return fail(SPT_ERR_INVALID_ARG, "NULL factors or lambda");
     for (int w = 0; w < t->N; ++w)
         if (!factors[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor matrix");
+    for (int w = 0; w < t->N; ++w)
+        if (!aligned16(factors[w])) return fail(SPT_ERR_INVALID_ARG, "factor matrices must be 16-byte aligned");
     if (!t->copies && t->cur_mode != 0) return fail(SPT_ERR_STATE, "stream must be in mode 0's order");
     if (fit && t->norm_sq <= 0.0) return fail(SPT_ERR_INVALID_ARG, "fit undefined for a zero tensor");
     hipStream_t s = (hipStream_t)stream;
@@ -883,6 +893,8 @@ spt_status grad_args(spt_tensor_t t, const void* const* factors, spt_dtype fdtyp
     if (!factors) return fail(SPT_ERR_INVALID_ARG, "NULL factors");
     for (int w = 0; w < t->N; ++w)
         if (!factors[w]) return fail(SPT_ERR_INVALID_ARG, "NULL factor matrix");
+    for (int w = 0; w < t->N; ++w)
+        if (!aligned16(factors[w])) return fail(SPT_ERR_INVALID_ARG, "factor matrices must be 16-byte aligned");
     if (!t->copies && t->cur_mode != 0) return fail(SPT_ERR_STATE, "stream must be in mode 0's order");
     spt_status st = ensure_carry(t, rank);
     if (st != SPT_OK) return st;
@@ -958,6 +970,8 @@ spt_status spt_cp_adjoint(spt_tensor_t t, const void* const* factors, spt_dtype 
     if (!grads) return fail(SPT_ERR_INVALID_ARG, "NULL grads");
     for (int w = 0; w < t->N; ++w)
         if (!grads[w]) return fail(SPT_ERR_INVALID_ARG, "NULL gradient matrix");
+    for (int w = 0; w < t->N; ++w)
+        if (!aligned16(grads[w])) return fail(SPT_ERR_INVALID_ARG, "gradient matrices must be 16-byte aligned");
     if (t->res_rank != rank) return fail(SPT_ERR_STATE, "no residual stream of this rank: call spt_cp_loss first");
     return run_adjoint(t, factors, rank, grads, (hipStream_t)stream);
 }
@@ -970,6 +984,8 @@ spt_status spt_cp_gradient(spt_tensor_t t, const void* const* factors, spt_dtype
     if (!grads || !loss) return fail(SPT_ERR_INVALID_ARG, "NULL grads or loss");
     for (int w = 0; w < t->N; ++w)
         if (!grads[w]) return fail(SPT_ERR_INVALID_ARG, "NULL gradient matrix");
+    for (int w = 0; w < t->N; ++w)
+        if (!aligned16(grads[w])) return fail(SPT_ERR_INVALID_ARG, "gradient matrices must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     if ((st = run_loss(t, factors, rank, loss, s)) != SPT_OK) return st;
     return run_adjoint(t, factors, rank, grads, s);

@@ -266,6 +266,29 @@ def test_edge_cases(lib, kind):
     t.free()
 
 
+def test_misaligned_factor_or_output_is_rejected(lib):
+    """Rows move as 16-byte vectors: a factor, output or gradient matrix that
+    does not start on a 16-byte boundary is refused before any launch."""
+    dims, R = (50, 40, 30), 8
+    idx, val = synth.random_coo(dims, 500, seed=4)
+    t = T(lib, dims, idx, val)
+    Y = synth.random_factors(dims, R, seed=6)
+    pad = [np.zeros(y.size + 4, np.float32) for y in Y]  # room for a 4-byte shift
+    ptrs = [p.ctypes.data for p in pad]
+    assert all(p % 16 == 0 for p in ptrs)
+    out = np.zeros(dims[0] * R + 4, np.float32)
+    L = lib
+    bad = (ctypes.c_void_p * 3)(ptrs[0], ptrs[1] + 4, ptrs[2])
+    good = (ctypes.c_void_p * 3)(*ptrs)
+    assert L.spt_mttkrp(t.h, 0, bad, 0, R, out.ctypes.data, FUSE, None) != 0
+    assert b"16-byte aligned" in L.spt_last_error()
+    assert L.spt_mttkrp(t.h, 0, good, 0, R, out.ctypes.data + 4, FUSE, None) != 0
+    assert b"16-byte aligned" in L.spt_last_error()
+    assert L.spt_mttkrp_noalloc(t.h, 0, bad, 0, R, out.ctypes.data, FUSE, None) != 0
+    assert t.info().cur_mode == 0  # nothing ran
+    t.free()
+
+
 def test_copy_probe(lib):
     src = np.arange(4096 * 4, dtype=np.uint32)
     dst = np.zeros_like(src)
