@@ -275,6 +275,47 @@ def test_plan_invariants_and_stream_order_by_brute_force(dims, nnz, kappa, cap):
         assert p["order"][d].tolist() == sorted(range(nnz), key=key)
 
 
+@pytest.mark.parametrize("dims,nnz,kappa,cap", [((7, 6, 5), 120, 3, None), ((5, 4, 3, 3), 150, 4, 0),
+                                                ((4, 3, 3, 2, 2), 90, 5, None), ((30, 20), 300, 6, 5)])
+def test_stream_order_reading_consequences(dims, nnz, kappa, cap):
+    """What the within-partition order (the reading of Sec. 3.1 the design
+    takes) promises, checked on the plan's streams directly: the stream after
+    mode d's remap is mode d's stream stably re-sorted by (z, i) of mode d+1,
+    so N remaps return to mode 0's order; and the records that one source
+    partition sends to one destination row are consecutive there, in the
+    order the source stream holds them."""
+    idx, _ = synth.random_coo(dims, nnz, seed=11, dist="zipf", zipf_s=1.2)
+    p = oracle.plan(dims, idx, kappa, split_cap=cap)
+    N = len(dims)
+    z = p["part"]
+    for d in range(N):
+        nx = (d + 1) % N
+        src = p["order"][d]
+        pos = {int(e): k for k, e in enumerate(src)}
+        # stable re-sort of the source stream by the next mode's (z, i) alone
+        resorted = sorted(src.tolist(), key=lambda e: (int(z[nx][e]), int(idx[nx][e])))
+        assert resorted == p["order"][nx].tolist(), f"mode {d} -> {nx}"
+        # adjacency: within each destination row, the records of one source
+        # partition form one run, in source order
+        dst = p["order"][nx]
+        rows = idx[nx][dst]
+        parts = z[nx][dst]
+        start = 0
+        while start < nnz:
+            end = start
+            while end < nnz and rows[end] == rows[start] and parts[end] == parts[start]:
+                end += 1
+            seen = {}
+            for k in range(start, end):
+                e = int(dst[k])
+                zs = int(z[d][e])
+                if zs in seen:
+                    assert seen[zs] == k - 1, "a source partition's records are split inside a row"
+                    assert pos[e] > pos[int(dst[k - 1])]
+                seen[zs] = k
+            start = end
+
+
 def test_split_balances_a_hot_row():
     # one row with 60 % of the nonzeros: pure Alg. 1 cannot balance it, the
     # split extension brings the largest block to about nnz / kappa.
