@@ -49,7 +49,9 @@ __device__ __forceinline__ void mult_rows(const Rec<RW>& r, const ForwardArgs& a
 }
 
 // One nonzero per group of L = R/4 lanes; the group's partial dot products
-// are summed across its lanes with butterfly shuffles.
+// are summed across its lanes with butterfly shuffles.  The record of the
+// group's next nonzero is fetched before the current one's rows are
+// gathered, so each iteration waits for one round trip instead of two.
 template <int N, int R, int RW, int KIND>
 __global__ __launch_bounds__(256) void forward_kernel(const ForwardArgs a) {
     constexpr int L = R / 4;
@@ -57,10 +59,14 @@ __global__ __launch_bounds__(256) void forward_kernel(const ForwardArgs a) {
     __shared__ double red[256];
     const int tid = threadIdx.x;
     const int g = tid / L, li = tid % L;
+    const int64_t stride = (int64_t)gridDim.x * GPB;
     double loss = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * GPB + g; p < a.nnz; p += (int64_t)gridDim.x * GPB) {
-        Rec<RW> r;
-        load_rec<RW>(a.rec_in, p, r);
+    int64_t p = (int64_t)blockIdx.x * GPB + g;
+    Rec<RW> r{};
+    if (p < a.nnz) load_rec<RW>(a.rec_in, p, r);
+    for (; p < a.nnz; p += stride) {
+        Rec<RW> rn = r;
+        if (p + stride < a.nnz) load_rec<RW>(a.rec_in, p + stride, rn);
         float prod[4] = {1.f, 1.f, 1.f, 1.f};
         mult_rows<N, R, RW, KIND, 0>(r, a, li, prod);
         float m = (prod[0] + prod[1]) + (prod[2] + prod[3]);
@@ -74,6 +80,7 @@ __global__ __launch_bounds__(256) void forward_kernel(const ForwardArgs a) {
             store_rec<RW>(a.rec_res, p, o);
             loss += 0.5 * (double)res * (double)res;
         }
+        r = rn;
     }
     red[tid] = loss;
     __syncthreads();

@@ -94,7 +94,7 @@ def lib(request, tmp_path_factory):
 
 # the binding's mirrors of the header's structs (their layout is checked
 # against the header in test_abi)
-from paper_2405_08470_amd.spmttkrp import spt_info as Info, spt_opts as Opts  # noqa: E402
+from paper_2405_08470_amd.spmttkrp import LAYOUTS, spt_info as Info, spt_opts as Opts  # noqa: E402
 
 
 class T:
@@ -147,7 +147,6 @@ def bf16_bits(y):
     return (oracle.bf16_round(y).view(np.uint32) >> 16).astype(np.uint16)
 
 
-LAYOUTS = {"auto": 0, "word32": 1, "half16": 2, "packed": 3, "compact": 4}
 CASES = [
     # name, dims, nnz, dist, zipf_s, R, kappa, split_cap, layout (auto: the
     # 12-byte records wherever the indices fit 64 bits)
