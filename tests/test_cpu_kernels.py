@@ -265,6 +265,39 @@ def test_edge_cases(lib, kind):
     t.free()
 
 
+@pytest.mark.parametrize("dims,layout,rb", [
+    ((5000, 4000), "auto", 12),                     # 32-bit indices in 64 bits
+    ((3000, 2500, 1000, 60), "auto", 12),           # 16-bit fields
+    ((100_000, 80_000, 3000), "auto", 12),          # 17 + 17 + 12 bit fields
+    ((3_000_000, 3_000_000, 3_000_000), "auto", 16),  # 66 index bits: 16-byte words
+    ((70_000, 70_000, 70_000, 70_000), "auto", 16),   # 68 bits: packed in 96
+    ((3_000_000, 3_000_000, 3_000_000), "compact", None),
+    ((70_000, 70_000, 70_000, 70_000), "compact", None),
+    ((9, 8, 7, 6, 5, 4, 3, 2), "compact", 12),
+])
+def test_record_layout_choice(lib, dims, layout, rb):
+    """The automatic layout takes the 12-byte record whenever the indices fit
+    64 bits; asking for it where they do not fit is refused."""
+    idx, val = synth.random_coo(dims, 300, seed=5)
+    if rb is None:
+        o = Opts()
+        o.layout = LAYOUTS[layout]
+        d = np.ascontiguousarray(dims, dtype=np.int64)
+        i = np.ascontiguousarray(idx, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float32)
+        h = ctypes.c_void_p()
+        rc = lib.spt_tensor_load_coo(len(dims), d.ctypes.data, i.shape[1], i.ctypes.data, v.ctypes.data,
+                                     ctypes.byref(o), None, ctypes.byref(h))
+        assert rc != 0 and b"layout" in lib.spt_last_error()
+        return
+    t = T(lib, dims, idx, val, layout=LAYOUTS[layout])
+    assert t.info().record_bytes == rb
+    gi, gv, _ = t.records()
+    o = oracle.plan(dims, idx, t.info().kappa)["order"][0]
+    assert np.array_equal(gi, idx[:, o]) and np.array_equal(gv, val[o])
+    t.free()
+
+
 def test_misaligned_factor_or_output_is_rejected(lib):
     """Rows move as 16-byte vectors: a factor, output or gradient matrix that
     does not start on a 16-byte boundary is refused before any launch."""
